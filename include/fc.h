@@ -1,0 +1,231 @@
+/*
+ * fc.h -- C ABI of the MI355X (gfx950) solver for similarity-based fuzzy
+ * clustering by accelerated gradient projection.
+ *
+ * Problem (P), section 2: given a sparse symmetric similarity S (N x N) and a
+ * number of clusters C, minimise f(X) = ||S - X^T X||_F^2 over membership
+ * matrices X whose N columns lie on the unit simplex of R^C.  This library
+ * stores X^T: U is an n x c row-major matrix whose row i is the column x_i of
+ * the paper (n = N, c = C), so every row of U is non-negative and sums to 1.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Pointers named "device" must be HIP device memory (hipMalloc'd, or a
+ *   torch CUDA tensor's data_ptr()).  Pointers named "host" are host memory.
+ * - `stream` is a hipStream_t passed as void*; NULL means the default stream.
+ *   All device work is enqueued on that stream.  Calls that return scalars
+ *   (fc_step, fc_solve, fc_objective, fc_gram, fc_spectral_norm, fc_create)
+ *   synchronise that stream before returning; fc_project, fc_spmm and
+ *   fc_get_u only enqueue work.
+ * - S is borrowed: the caller keeps its arrays alive and unmodified until
+ *   fc_destroy of every solver built on it.  U0 is copied at fc_create.
+ *   Output buffers are caller-allocated.
+ * - Every call returns an fc_status; no C++ exception crosses this ABI.
+ *   On an error the thread-local message of fc_last_error() says what failed.
+ *   A solver handle stays valid after FC_ERR_NONFINITE or FC_ERR_STEP and
+ *   keeps the last accepted iterate.
+ * - One handle must not be used by two threads at once; distinct handles
+ *   are independent.
+ * - Arithmetic: FC_PREC_FP64 computes in double; FC_PREC_FP32 stores U, the
+ *   products S U and S values in float and accumulates in float, with every
+ *   reduction across rows (Gram matrices, the trace term, the line-search
+ *   quantities, the simplex threshold sums) carried in double;
+ *   FC_PREC_MIXED additionally stores S values as half and keeps a bfloat16
+ *   copy of U for the sparse product.
+ */
+#ifndef FC_H
+#define FC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FC_OK = 0,
+    FC_ERR_INVALID_ARG = 1,   /* a pointer, size or option is out of range */
+    FC_ERR_UNSUPPORTED = 2,   /* a valid request this build does not implement */
+    FC_ERR_OUT_OF_MEMORY = 3, /* a device allocation failed */
+    FC_ERR_DEVICE = 4,        /* a HIP runtime call failed */
+    FC_ERR_NONFINITE = 5,     /* the objective or an iterate became NaN/Inf */
+    FC_ERR_STEP = 6,          /* backtracking could not find an acceptable L */
+    FC_ERR_NOT_SYMMETRIC = 7  /* validation found S != S^T or a bad CSR */
+} fc_status;
+
+typedef enum { FC_F64 = 0, FC_F32 = 1, FC_F16 = 2, FC_BF16 = 3 } fc_dtype;
+typedef enum { FC_PREC_FP64 = 0, FC_PREC_FP32 = 1, FC_PREC_MIXED = 2 } fc_precision;
+
+/* Diagonal of the similarity.  The objective sums over all pairs (i, j)
+ * including i = j (problem (P)).  FC_DIAG_STORED uses the CSR arrays as S.
+ * FC_DIAG_UNIT uses S + I: the paper builds S as the adjacency matrix plus
+ * ones on the diagonal (Example 4.1; hyperparameters of section 5), and in
+ * this mode the CSR arrays must not store diagonal entries. */
+typedef enum { FC_DIAG_STORED = 0, FC_DIAG_UNIT = 1 } fc_diag;
+
+/* Step rule.  FC_STEP_FIXED: a constant step size tau (Alg. 2-4), or the
+ * per-iteration schedule of fc_options.step_schedule.  FC_STEP_BACKTRACK:
+ * L = 1/tau grows by eta until the sufficient-decrease test
+ * f(p) <= f(Y) + <grad f(Y), p - Y> + (L/2) ||p - Y||^2 holds (the FISTA
+ * backtracking rule of Beck and Teboulle, which the paper cites for FISTA). */
+typedef enum { FC_STEP_FIXED = 0, FC_STEP_BACKTRACK = 1 } fc_step_rule;
+
+typedef enum {
+    FC_STOP_NONE = 0,     /* still running / stopped by the iteration budget */
+    FC_STOP_MAXITER = 1,  /* fc_options.max_iter accepted iterations done */
+    FC_STOP_LOSS = 2,     /* loss decrease <= tol_loss (Alg. 3 and Alg. 4) */
+    FC_STOP_PGRAD = 3,    /* gradient-mapping norm <= tol_pgrad * first one */
+    FC_STOP_ERROR = 4     /* FC_ERR_NONFINITE or FC_ERR_STEP */
+} fc_stop_reason;
+
+/* Symmetric sparse similarity in CSR form (device arrays).  row_ptr has
+ * n + 1 int64 entries with row_ptr[0] = 0 and row_ptr[n] = nnz; col_idx has
+ * nnz int32 column indices in [0, n); values has nnz entries of
+ * values_dtype (FC_F64, FC_F32 or FC_F16).  Column order within a row is
+ * free.  S must equal S^T: the gradient formula of eq. (gradient_matrix)
+ * holds only for symmetric S. */
+typedef struct {
+    int64_t n;
+    int64_t nnz;
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    const void *values;
+    fc_dtype values_dtype;
+} fc_csr;
+
+typedef struct {
+    uint32_t struct_size;      /* sizeof(fc_options), set by fc_options_default */
+    int32_t c;                 /* number of clusters C, 1 <= c <= 64 */
+    fc_precision precision;
+    fc_diag diag;
+    int32_t accelerate;        /* 1: parallel FISTA (Alg. 4); 0: parallel GPA (Alg. 2/3) */
+    fc_step_rule step_rule;
+    double step;               /* FC_STEP_FIXED: tau; <= 0 means tau = 1/L_thm with
+                                  L_thm = 4 ||S||_2 + 12 n (Theorem 3.1), ||S||_2 by
+                                  power iteration on the device */
+    double L0;                 /* FC_STEP_BACKTRACK: initial L; <= 0 means L_thm / 100 */
+    double eta;                /* FC_STEP_BACKTRACK: growth factor of L (> 1; default 2) */
+    int32_t max_iter;          /* accepted-iteration budget of fc_solve */
+    int32_t check_every;       /* fc_solve/fc_step read the device state back every
+                                  check_every launched trials (default 16) */
+    double tol_loss;           /* stop when f(Xbar_{n-1}) - f(Xbar_n) <= tol_loss
+                                  (Alg. 3/4); NaN disables (default) */
+    double tol_pgrad;          /* stop when r_n <= tol_pgrad * r_1, with
+                                  r_n = ||Y_n - Xbar_n||_F / tau_n; 0 disables */
+    int32_t validate;          /* 1: check CSR structure and symmetry at fc_create */
+    int32_t reserved0;
+    const double *step_schedule; /* host: tau_n for n = 1..step_schedule_len, copied at
+                                    fc_create; used by FC_STEP_FIXED when non-NULL */
+    int32_t step_schedule_len;
+    int32_t reserved1;
+} fc_options;
+
+/* Per-solver progress, returned by fc_step and fc_solve. */
+typedef struct {
+    int32_t iter;          /* accepted iterations so far */
+    int32_t trials;        /* step-size trials so far (= iter for fixed steps) */
+    int32_t stop_reason;   /* fc_stop_reason */
+    int32_t reserved;
+    double f;              /* f(Xbar_iter), structured objective, double */
+    double f_prev;         /* f(Xbar_{iter-1}) */
+    double L;              /* 1 / tau of the last accepted step */
+    double t;              /* inertial parameter t_{iter+1} of Alg. 4 */
+    double beta;           /* (t_iter - 1) / t_{iter+1}, weight of the next extrapolation */
+    double pgrad;          /* r_iter */
+    double pgrad_rel;      /* r_iter / r_1 */
+} fc_info;
+
+typedef struct fc_solver fc_solver;
+
+/* Fill *opt with defaults: c = 0 (must be set), FP32, unit diagonal,
+ * FISTA, fixed step with tau from Theorem 3.1, eta = 2, max_iter = 100,
+ * check_every = 16, tol_loss = NaN, tol_pgrad = 0, no validation. */
+void fc_options_default(fc_options *opt);
+
+/* Set up a solve of problem (P) (Alg. 4, initialisation): copies U0
+ * (device, n x c row-major of u0_dtype; NULL = the constant 1/c start) to
+ * Xbar_0, computes ||S||_F^2 and, if needed, ||S||_2 by power iteration,
+ * and evaluates f(Xbar_0).  Allocates all device work buffers (six n x c
+ * iterate/product buffers, S copies for mixed precision, partial sums).
+ * Errors: FC_ERR_INVALID_ARG (NULL pointers, n < 1, c outside [1, 64],
+ * dtype/precision mismatch), FC_ERR_NOT_SYMMETRIC (validate = 1),
+ * FC_ERR_OUT_OF_MEMORY, FC_ERR_DEVICE.  *out is NULL on error. */
+fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0,
+                    fc_dtype u0_dtype, void *stream, fc_solver **out);
+
+/* Run exactly `iters` more accepted iterations of Alg. 4 (Alg. 2/3 when
+ * accelerate = 0) unless a stop rule fires first.  One iteration: the
+ * extrapolated point Y_n, the gradient -4 (S Y_n - Y_n Y_n^T Y_n) of
+ * eq. (gradient_column), the step and the row-wise simplex projection
+ * (Alg. 1), and the structured loss of Alg. 3 at the new iterate.  Fills
+ * *info (may be NULL).  Returns FC_ERR_NONFINITE or FC_ERR_STEP when the
+ * iteration failed; the handle then holds the last good iterate. */
+fc_status fc_step(fc_solver *h, int32_t iters, fc_info *info);
+
+/* Iterate until a stop rule fires or max_iter accepted iterations are
+ * done (counted from fc_create).  Same errors as fc_step. */
+fc_status fc_solve(fc_solver *h, fc_info *info);
+
+/* Copy the current iterate Xbar (n x c, row-major, dense) to U_out (device)
+ * as FC_F64 or FC_F32.  Enqueued on the solver's stream. */
+fc_status fc_get_u(const fc_solver *h, void *U_out, fc_dtype dtype);
+
+/* Per-iteration history (host outputs, each may be NULL): f_log[0..k] the
+ * loss of Xbar_0..Xbar_k, step_log[1..k] the accepted tau_n,
+ * trials_log[1..k] the trials per iteration, r_log[1..k] the gradient-
+ * mapping norms.  `cap` is the capacity of each array in entries; *count
+ * receives k + 1.  The solver keeps the history of its first 65,536
+ * iterations. */
+fc_status fc_get_history(const fc_solver *h, int32_t cap, double *f_log,
+                         double *step_log, int32_t *trials_log, double *r_log,
+                         int32_t *count);
+
+/* Checkpoint: serialise the solver state (Xbar_n, Xbar_{n-1}, t, L, f, the
+ * iteration counters) into host memory.  With buf = NULL, *bytes receives
+ * the size needed.  fc_set_state restores a state taken from a solver with
+ * the same S, n, c and options; the products S Xbar are recomputed. */
+fc_status fc_get_state(const fc_solver *h, void *buf, size_t *bytes);
+fc_status fc_set_state(fc_solver *h, const void *buf, size_t bytes);
+
+void fc_destroy(fc_solver *h);
+
+/* Structured objective of Alg. 3 for a given U (device, n x c row-major of
+ * u_dtype = FC_F64 or FC_F32): f = ||S||_F^2 + ||U^T U||_F^2
+ * - 2 sum_i <u_i, (S U)_i>, computed in the precision of u_dtype with the
+ * sums across rows in double.  *f_out is a host double. */
+fc_status fc_objective(const fc_csr *S, fc_diag diag, const void *U,
+                       fc_dtype u_dtype, int32_t c, void *stream, double *f_out);
+
+/* Row-wise Euclidean projection onto the unit simplex (Alg. 1 applied to
+ * every row; section 2, "Projection onto Omega"): out_i = P(V_i).  V and out
+ * are device arrays of `rows` rows with leading dimension ld >= c (in
+ * elements) of dtype FC_F64 or FC_F32; in-place (out == V) is allowed.
+ * The threshold sums are carried in double.  Asynchronous. */
+fc_status fc_project(const void *V, void *out, fc_dtype dtype, int64_t rows,
+                     int32_t c, int64_t ld, void *stream);
+
+/* Kernel-level entry points (the steps of one iteration, for testing and
+ * profiling).  fc_spmm: Z = S_eff U for U, Z device n x c row-major of
+ * dtype (FC_F64/FC_F32; S values must be of the same type, or FC_F16 with
+ * FC_F32 U), i.e. row i of Z is the product X s_i of eq. (gradient_column);
+ * asynchronous.  fc_gram: G = U^T U (the paper's share = X X^T, Alg. 2)
+ * into a host double c x c array.  fc_spectral_norm: ||S_eff||_2 by power
+ * iteration from the normalised ones vector (relative change < rtol or
+ * max_iter products), for the step bound of Theorem 3.1. */
+fc_status fc_spmm(const fc_csr *S, fc_diag diag, const void *U, void *Z,
+                  fc_dtype dtype, int32_t c, void *stream);
+fc_status fc_gram(const void *U, fc_dtype dtype, int64_t n, int32_t c,
+                  void *stream, double *G_out);
+fc_status fc_spectral_norm(const fc_csr *S, fc_diag diag, int32_t max_iter,
+                           double rtol, void *stream, double *norm_out,
+                           int32_t *iters_out);
+
+/* Thread-local message of the last failed call on this thread ("" if none). */
+const char *fc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FC_H */

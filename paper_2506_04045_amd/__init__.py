@@ -1,0 +1,243 @@
+"""MI355X (gfx950) solver for similarity-based fuzzy clustering.
+
+Python binding of the C ABI in ``include/fc.h``.  Every function here only
+marshals arguments: tensors must already live on the GPU (torch is used for
+device memory and streams), and every step of the computation runs in the
+HIP kernels of ``libfc.so``.
+
+Problem (P), section 2 of the paper: minimise ||S - U U^T||_F^2 over
+row-stochastic U (n x c); the paper's membership matrix is X = U^T.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+__all__ = ["Solver", "Info", "objective", "project", "spmm", "gram", "spectral_norm",
+           "library_path"]
+
+_PREC = {"fp64": N.FC_PREC_FP64, "fp32": N.FC_PREC_FP32, "mixed": N.FC_PREC_MIXED}
+_DIAG = {"stored": N.FC_DIAG_STORED, "unit": N.FC_DIAG_UNIT}
+_DT = {torch.float64: N.FC_F64, torch.float32: N.FC_F32, torch.float16: N.FC_F16}
+
+
+def library_path() -> str:
+    N.load()
+    return N.LIB_PATH
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _dev(t: torch.Tensor, name: str, dtypes=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if dtypes is not None and t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    return t
+
+
+class _CsrView:
+    """Holds the tensors referenced by an fc_csr so they stay alive."""
+
+    def __init__(self, row_ptr, col_idx, val):
+        self.row_ptr = _dev(row_ptr, "row_ptr", (torch.int64,))
+        self.col_idx = _dev(col_idx, "col_idx", (torch.int32,))
+        self.val = _dev(val, "val", (torch.float64, torch.float32, torch.float16))
+        n = self.row_ptr.numel() - 1
+        if n < 1:
+            raise ValueError("row_ptr must have at least 2 entries")
+        if self.col_idx.numel() != self.val.numel():
+            raise ValueError("col_idx and val differ in length")
+        self.c = N.CSR(n, self.col_idx.numel(), self.row_ptr.data_ptr(),
+                       self.col_idx.data_ptr(), self.val.data_ptr(), _DT[self.val.dtype])
+
+    @property
+    def n(self) -> int:
+        return int(self.c.n)
+
+
+@dataclass
+class Info:
+    iter: int
+    trials: int
+    stop_reason: int
+    f: float
+    f_prev: float
+    L: float
+    t: float
+    beta: float
+    pgrad: float
+    pgrad_rel: float
+
+    @staticmethod
+    def of(i: N.Info) -> "Info":
+        return Info(i.iter, i.trials, i.stop_reason, i.f, i.f_prev, i.L, i.t, i.beta, i.pgrad,
+                    i.pgrad_rel)
+
+
+class Solver:
+    """One solve of problem (P): fc_create / fc_step / fc_solve / fc_get_u."""
+
+    def __init__(self, row_ptr, col_idx, val, c: int, U0=None, *, precision: str = "fp32",
+                 diag: str = "unit", accelerate: bool = True, step: float = 0.0,
+                 backtrack: bool = False, L0: float = 0.0, eta: float = 2.0,
+                 max_iter: int = 100, check_every: int = 16, tol_loss: float = math.nan,
+                 tol_pgrad: float = 0.0, validate: bool = False, step_schedule=None,
+                 stream=None):
+        lib = N.load()
+        self._csr = _CsrView(row_ptr, col_idx, val)
+        self.n, self.c = self._csr.n, int(c)
+        self.precision = precision
+        opt = N.default_options()
+        opt.c = self.c
+        opt.precision = _PREC[precision]
+        opt.diag = _DIAG[diag]
+        opt.accelerate = int(bool(accelerate))
+        opt.step_rule = N.FC_STEP_BACKTRACK if backtrack else N.FC_STEP_FIXED
+        opt.step = float(step)
+        opt.L0 = float(L0)
+        opt.eta = float(eta)
+        opt.max_iter = int(max_iter)
+        opt.check_every = int(check_every)
+        opt.tol_loss = float(tol_loss)
+        opt.tol_pgrad = float(tol_pgrad)
+        opt.validate = int(bool(validate))
+        self._sched = None
+        if step_schedule is not None:
+            self._sched = np.ascontiguousarray(step_schedule, dtype=np.float64)
+            opt.step_schedule = self._sched.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            opt.step_schedule_len = int(self._sched.shape[0])
+        u0_ptr, u0_dt = None, N.FC_F32
+        if U0 is not None:
+            U0 = _dev(U0, "U0", (torch.float64, torch.float32))
+            if tuple(U0.shape) != (self.n, self.c):
+                raise ValueError(f"U0 must be ({self.n}, {self.c})")
+            u0_ptr, u0_dt = U0.data_ptr(), _DT[U0.dtype]
+        self._stream = stream
+        h = ctypes.c_void_p()
+        N.check(lib.fc_create(ctypes.byref(self._csr.c), ctypes.byref(opt), u0_ptr, u0_dt,
+                              _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    def _handle(self):
+        if self._h is None:
+            raise RuntimeError("solver destroyed")
+        return self._h
+
+    def step(self, iters: int) -> Info:
+        info = N.Info()
+        N.check(N.load().fc_step(self._handle(), int(iters), ctypes.byref(info)))
+        return Info.of(info)
+
+    def solve(self) -> Info:
+        info = N.Info()
+        N.check(N.load().fc_solve(self._handle(), ctypes.byref(info)))
+        return Info.of(info)
+
+    def info(self) -> Info:
+        return self.step(0)
+
+    def get_u(self, dtype=torch.float32) -> torch.Tensor:
+        out = torch.empty(self.n, self.c, dtype=dtype, device="cuda")
+        N.check(N.load().fc_get_u(self._handle(), out.data_ptr(), _DT[dtype]))
+        return out
+
+    def history(self, cap: int | None = None) -> dict:
+        cap = cap or 65536
+        f = np.zeros(cap)
+        tau = np.zeros(cap)
+        trials = np.zeros(cap, dtype=np.int32)
+        r = np.zeros(cap)
+        cnt = ctypes.c_int32(0)
+        N.check(N.load().fc_get_history(self._handle(), cap, f.ctypes.data, tau.ctypes.data,
+                                        trials.ctypes.data, r.ctypes.data, ctypes.byref(cnt)))
+        k = cnt.value
+        return dict(f=f[:k].copy(), tau=tau[:k].copy(), trials=trials[:k].copy(), r=r[:k].copy())
+
+    def close(self) -> None:
+        if self._h is not None:
+            N.load().fc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+def objective(row_ptr, col_idx, val, U: torch.Tensor, diag: str = "unit", stream=None) -> float:
+    """Structured objective of Alg. 3 (fc_objective)."""
+    csr = _CsrView(row_ptr, col_idx, val)
+    U = _dev(U, "U", (torch.float64, torch.float32))
+    out = ctypes.c_double(0.0)
+    N.check(N.load().fc_objective(ctypes.byref(csr.c), _DIAG[diag], U.data_ptr(), _DT[U.dtype],
+                                  U.shape[1], _stream_ptr(stream), ctypes.byref(out)))
+    return float(out.value)
+
+
+def project(V: torch.Tensor, out: torch.Tensor | None = None, c: int | None = None,
+            stream=None) -> torch.Tensor:
+    """Row-wise projection onto the unit simplex (fc_project).  V is (rows, ld)
+    and the first c columns of each row are projected."""
+    V = _dev(V, "V", (torch.float64, torch.float32))
+    if V.dim() != 2:
+        raise ValueError("V must be 2-D")
+    if out is None:
+        out = torch.empty_like(V)
+    out = _dev(out, "out", (V.dtype,))
+    rows, ld = V.shape
+    c = ld if c is None else int(c)
+    N.check(N.load().fc_project(V.data_ptr(), out.data_ptr(), _DT[V.dtype], rows, c, ld,
+                                _stream_ptr(stream)))
+    return out
+
+
+def spmm(row_ptr, col_idx, val, U: torch.Tensor, diag: str = "unit", stream=None) -> torch.Tensor:
+    """Z = S_eff U (fc_spmm)."""
+    csr = _CsrView(row_ptr, col_idx, val)
+    U = _dev(U, "U", (torch.float64, torch.float32))
+    Z = torch.empty_like(U)
+    N.check(N.load().fc_spmm(ctypes.byref(csr.c), _DIAG[diag], U.data_ptr(), Z.data_ptr(),
+                             _DT[U.dtype], U.shape[1], _stream_ptr(stream)))
+    return Z
+
+
+def gram(U: torch.Tensor, stream=None) -> np.ndarray:
+    """G = U^T U in double (fc_gram), returned as a host array."""
+    U = _dev(U, "U", (torch.float64, torch.float32))
+    n, c = U.shape
+    G = np.zeros((c, c))
+    N.check(N.load().fc_gram(U.data_ptr(), _DT[U.dtype], n, c, _stream_ptr(stream),
+                             G.ctypes.data))
+    return G
+
+
+def spectral_norm(row_ptr, col_idx, val, diag: str = "unit", max_iter: int = 1000,
+                  rtol: float = 1e-12, stream=None):
+    """(||S_eff||_2, power iterations) (fc_spectral_norm)."""
+    csr = _CsrView(row_ptr, col_idx, val)
+    out = ctypes.c_double(0.0)
+    it = ctypes.c_int32(0)
+    N.check(N.load().fc_spectral_norm(ctypes.byref(csr.c), _DIAG[diag], int(max_iter),
+                                      float(rtol), _stream_ptr(stream), ctypes.byref(out),
+                                      ctypes.byref(it)))
+    return float(out.value), int(it.value)

@@ -1,0 +1,1181 @@
+// fc_kernels.hpp -- gfx950 (MI355X) kernels of the fuzzy-clustering solver.
+//
+// Problem (P), section 2: minimise ||S - U U^T||_F^2 over row-stochastic
+// U (n x c), i.e. the paper's X = U^T with columns on the unit simplex.
+// One accelerated gradient-projection iteration (Alg. 4) is built here from
+//   * k_spmm   : Z = S_eff U, the products X s_i of eq. (gradient_column),
+//                plus the per-row terms <u_i, (S U)_i> of the loss (Alg. 3)
+//   * k_fused  : extrapolation Y = (1+beta) Xbar_c - beta Xbar_p and, by
+//                linearity of S, S Y from the stored products; the gradient
+//                -4 (S Y - Y G_Y) with Y G_Y on MFMA; the step; the row-wise
+//                simplex projection (Alg. 1 semantics, computed by Michelot's
+//                finite pivoting); Gram matrices of the new iterate and of
+//                the next extrapolated point on MFMA; line-search sums
+//   * k_control: one workgroup that turns the reduced sums into the loss,
+//                the acceptance test, the inertial update of Alg. 4 and the
+//                stop tests, entirely on the device.
+//
+// Layout: every n x c matrix is stored row-major with a padded width CP (a
+// power of two >= max(c, 4)); padded columns hold zeros.  Reductions across
+// rows are done per workgroup in double and then combined in a fixed order,
+// so results do not depend on scheduling.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fc {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Acc4;
+template <> struct Acc4<float> { typedef floatx4 type; };
+template <> struct Acc4<double> { typedef doublex4 type; };
+
+// 16x16x4 matrix-core product, D = A B + C.  Operand layout for lane l:
+// A[l % 16][l / 16], B[l / 16][l % 16]; result register q of lane l holds
+// D[4 (l / 16) + q][l % 16].
+__device__ __forceinline__ floatx4 mfma16x16x4(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ doublex4 mfma16x16x4(double a, double b, doublex4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ __forceinline__ float to_f32(T v) { return (float)v; }
+template <> __device__ __forceinline__ float to_f32<__half>(__half v) { return __half2float(v); }
+template <> __device__ __forceinline__ float to_f32<__hip_bfloat16>(__hip_bfloat16 v) {
+    return __bfloat162float(v);
+}
+
+__device__ __forceinline__ double shfl_xor_d(double v, int m) { return __shfl_xor(v, m, 64); }
+__device__ __forceinline__ float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, 64); }
+
+// ---------------------------------------------------------------------------
+// Device-resident solver state.  Written by k_control (and by the host only
+// between launches); read by every kernel of an iteration.
+// ---------------------------------------------------------------------------
+enum { ROLE_C = 0, ROLE_P = 1, ROLE_N = 2 };
+enum { ERR_NONE = 0, ERR_NONFINITE = 5, ERR_STEP = 6 };
+enum { STOP_NONE = 0, STOP_MAXITER = 1, STOP_LOSS = 2, STOP_PGRAD = 3, STOP_ERROR = 4 };
+
+struct DevState {
+    int32_t iter;           // accepted iterations
+    int32_t target;         // kernels work while iter < target
+    int32_t active;         // 1 while iterating
+    int32_t stop_reason;
+    int32_t trials;         // trials launched and evaluated
+    int32_t trial_in_iter;  // trial number within the current iteration (1-based)
+    int32_t role[3];        // ring slots of Xbar_c (current), Xbar_p (previous), trial
+    int32_t error;
+    int32_t max_iter;
+    int32_t sched_len;
+    int32_t accelerate;
+    int32_t backtrack;
+    int32_t c;
+    int32_t hist_cap;
+    double L, tau;          // current trial: tau = 1/L
+    double t;               // t_n of Alg. 4 (iteration n = iter + 1)
+    double beta;            // Y_n = Xbar_c + beta (Xbar_c - Xbar_p)
+    double beta_next;       // weight of the next extrapolation (for G of Y_{n+1})
+    double f, f_prev;       // f(Xbar_iter), f(Xbar_{iter-1})
+    double r1, r;           // first and latest gradient-mapping norms
+    double s2;              // ||S_eff||_F^2
+    double mu;              // mean removed from G_Y before the product Y G_Y
+    double tol_loss, tol_pgrad, eta;
+    double tau0;            // constant step
+    double tr_y_last;       // diagnostics of the last trial
+    double df_last, rhs_last;
+};
+
+// Partial-sum layout of the fused kernel: three CPM x CPM matrices
+// (Gram of the trial point, Gram of the next extrapolated point, and the
+// line-search cross sum (p + y)^T (p - y)) followed by FUSED_NSCAL scalars.
+enum { FS_TRY = 0, FS_LIN = 1, FS_SQ = 2, FS_CORR = 3, FS_BAD = 4, FUSED_NSCAL = 8 };
+template <int CPM> struct FusedLayout {
+    static constexpr int MAT = CPM * CPM;
+    static constexpr int NE = 3 * MAT + FUSED_NSCAL;
+};
+
+// ---------------------------------------------------------------------------
+// Deterministic column reduction: out[e] = sum_p in[p * ld + e] for
+// e < ne, p < np.  A workgroup owns EB consecutive entries; its 256 threads
+// split the p range into 256/EB fixed chunks that are combined in order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_reduce_cols(const double *__restrict__ in, int64_t np,
+                                                     int64_t ld, int64_t ne,
+                                                     double *__restrict__ out, int eb) {
+    __shared__ double sh[256];
+    const int tid = threadIdx.x;
+    const int el = tid % eb, chunk = tid / eb, nchunk = 256 / eb;
+    const int64_t e = (int64_t)blockIdx.x * eb + el;
+    double acc = 0.0;
+    if (e < ne) {
+        const int64_t per = (np + nchunk - 1) / nchunk;
+        const int64_t p0 = chunk * per;
+        const int64_t p1 = p0 + per < np ? p0 + per : np;
+        for (int64_t p = p0; p < p1; ++p)
+            acc += in[p * ld + e];
+    }
+    sh[tid] = acc;
+    __syncthreads();
+    if (chunk == 0 && e < ne) {
+        double s = sh[el];
+        for (int k = 1; k < nchunk; ++k)
+            s += sh[k * eb + el];
+        out[e] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Copies between user matrices (rows x c, leading dimension ld, any of
+// f64/f32) and the padded internal layout (rows x CP).  A NULL source fills
+// the constant 1/c start point.
+// ---------------------------------------------------------------------------
+template <typename Tin, typename Tout>
+__global__ void k_pad_copy(const Tin *__restrict__ src, int64_t ld, Tout *__restrict__ dst,
+                           int64_t rows, int c, int cp) {
+    const int64_t total = rows * cp;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / cp;
+        const int k = (int)(idx % cp);
+        Tout v = (Tout)0;
+        if (k < c)
+            v = src ? (Tout)src[i * ld + k] : (Tout)(1.0 / c);
+        dst[idx] = v;
+    }
+}
+
+template <typename Tin, typename Tout>
+__global__ void k_unpad_copy(const Tin *__restrict__ src, int cp, Tout *__restrict__ dst,
+                             int64_t rows, int c) {
+    const int64_t total = rows * c;
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = idx / c;
+        const int k = (int)(idx % c);
+        dst[idx] = (Tout)src[i * cp + k];
+    }
+}
+
+template <typename T> __device__ __forceinline__ T from_f32(float v) { return (T)v; }
+template <> __device__ __forceinline__ __half from_f32<__half>(float v) { return __float2half_rn(v); }
+template <> __device__ __forceinline__ __hip_bfloat16 from_f32<__hip_bfloat16>(float v) {
+    return __float2bfloat16(v);
+}
+
+// Elementwise conversion (rounding to nearest) between storage types.
+template <typename Tin, typename Tout>
+__global__ void k_convert(const Tin *__restrict__ src, Tout *__restrict__ dst, int64_t count) {
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count;
+         idx += (int64_t)gridDim.x * blockDim.x)
+        dst[idx] = from_f32<Tout>(to_f32(src[idx]));
+}
+
+// ---------------------------------------------------------------------------
+// Sum of squared stored values (||S||_F^2 without the unit diagonal).
+// ---------------------------------------------------------------------------
+template <typename VS>
+__global__ __launch_bounds__(256) void k_sumsq(const VS *__restrict__ val, int64_t nnz,
+                                               double *__restrict__ part) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * 256) {
+        const double v = (double)to_f32(val[e]);
+        acc += v * v;
+    }
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = sh[0];
+}
+template <>
+__global__ __launch_bounds__(256) void k_sumsq<double>(const double *__restrict__ val, int64_t nnz,
+                                                       double *__restrict__ part) {
+    __shared__ double sh[256];
+    double acc = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < nnz; e += (int64_t)gridDim.x * 256)
+        acc += val[e] * val[e];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        part[blockIdx.x] = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// CSR validation: row_ptr monotone from 0 to nnz, columns in range, and
+// (diag_unit) no stored diagonal.  Symmetry is checked by k_check_symmetry:
+// for every stored (i, j, s) the row j must store (j, i) with the same value
+// (binary search; rows must be sorted for that check).
+// ---------------------------------------------------------------------------
+template <typename VS>
+__global__ void k_check_csr(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
+                            const VS *__restrict__ val, int64_t n, int64_t nnz, int diag_unit,
+                            int check_sym, int32_t *__restrict__ flags) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t b = row_ptr[i], e = row_ptr[i + 1];
+        if (b > e || b < 0 || e > nnz || (i == 0 && b != 0) || (i == n - 1 && e != nnz)) {
+            atomicOr(&flags[0], 1);
+            continue;
+        }
+        for (int64_t k = b; k < e; ++k) {
+            const int32_t j = col[k];
+            if (j < 0 || j >= n) {
+                atomicOr(&flags[0], 2);
+                break;
+            }
+            if (diag_unit && j == i)
+                atomicOr(&flags[0], 4);
+            if (k > b && col[k - 1] >= j)
+                atomicOr(&flags[0], 8);  // unsorted or duplicate: symmetry check unavailable
+            if (check_sym) {
+                int64_t lo = row_ptr[j], hi = row_ptr[j + 1] - 1;
+                bool found = false;
+                while (lo <= hi) {
+                    const int64_t mid = (lo + hi) >> 1;
+                    const int32_t cm = col[mid];
+                    if (cm == (int32_t)i) {
+                        found = to_f32(val[mid]) == to_f32(val[k]);
+                        break;
+                    }
+                    if (cm < (int32_t)i)
+                        lo = mid + 1;
+                    else
+                        hi = mid - 1;
+                }
+                if (!found)
+                    atomicOr(&flags[0], 16);
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Sparse product Z = S_eff U (one team of lanes per row).
+//
+// Each nonzero s_ij gathers the row u_j with GS lanes that each load 16
+// bytes, so a team of TEAM lanes works on SLOTS nonzeros of the row at once
+// and the slots are summed with cross-lane shuffles.  The epilogue adds u_i
+// for the unit diagonal, writes z_i and accumulates <u_i, z_i> in double
+// (the per-article products of Alg. 3); workgroups write one partial each.
+// Rows are visited in a grid-stride loop over blocks of ROWS_PER_WG rows.
+// ---------------------------------------------------------------------------
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+    typedef float4 type;
+    static constexpr int N = 4;
+};
+template <> struct Vec16<double> {
+    typedef double2 type;
+    static constexpr int N = 2;
+};
+template <> struct Vec16<__hip_bfloat16> {
+    typedef uint4 type;  // 8 bf16
+    static constexpr int N = 8;
+};
+
+template <typename TU, int CP> struct SpmmCfg {
+    static constexpr int VEC = Vec16<TU>::N;
+    static constexpr int GS = CP / VEC > 0 ? CP / VEC : 1;
+    static constexpr int TEAM = GS * 8 > 64 ? 64 : GS * 8;
+    static constexpr int SLOTS = TEAM / GS;
+    static constexpr int ROWS_PER_WG = 256 / TEAM;
+    static constexpr int LANE_ELEMS = CP / GS;  // elements of the row handled per lane
+};
+
+// Accumulator of LANE_ELEMS values in TA (float or double).
+template <typename TA, int NE> struct Frag {
+    TA v[NE];
+};
+
+template <typename TU, int NE> struct GatherLoad;
+template <int NE> struct GatherLoad<float, NE> {
+    __device__ __forceinline__ static void load(const float *p, float (&out)[NE]) {
+        static_assert(NE % 4 == 0, "float rows load in float4 pieces");
+#pragma unroll
+        for (int q = 0; q < NE / 4; ++q) {
+            const float4 t = reinterpret_cast<const float4 *>(p)[q];
+            out[4 * q + 0] = t.x;
+            out[4 * q + 1] = t.y;
+            out[4 * q + 2] = t.z;
+            out[4 * q + 3] = t.w;
+        }
+    }
+};
+template <int NE> struct GatherLoad<double, NE> {
+    __device__ __forceinline__ static void load(const double *p, double (&out)[NE]) {
+        static_assert(NE % 2 == 0, "double rows load in double2 pieces");
+#pragma unroll
+        for (int q = 0; q < NE / 2; ++q) {
+            const double2 t = reinterpret_cast<const double2 *>(p)[q];
+            out[2 * q + 0] = t.x;
+            out[2 * q + 1] = t.y;
+        }
+    }
+};
+template <int NE> struct GatherLoad<__hip_bfloat16, NE> {
+    __device__ __forceinline__ static void load(const __hip_bfloat16 *p, float (&out)[NE]) {
+        static_assert(NE % 8 == 0, "bf16 rows load in 8-element pieces");
+#pragma unroll
+        for (int q = 0; q < NE / 8; ++q) {
+            const uint4 t = reinterpret_cast<const uint4 *>(p)[q];
+            const uint32_t w[4] = {t.x, t.y, t.z, t.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                out[8 * q + 2 * h + 0] = __uint_as_float(w[h] << 16);
+                out[8 * q + 2 * h + 1] = __uint_as_float(w[h] & 0xffff0000u);
+            }
+        }
+    }
+};
+
+template <typename T> struct AccumOf { typedef T type; };
+template <> struct AccumOf<__hip_bfloat16> { typedef float type; };
+
+// TU: type of the gathered rows (f64, f32 or bf16); TZ: output type;
+// TX: type of the row u_i used by the epilogue (the master copy);
+// VS: type of the stored values.
+template <typename TU, typename TZ, typename TX, typename VS, int CP>
+__global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ row_ptr,
+                                              const int32_t *__restrict__ col,
+                                              const VS *__restrict__ val,
+                                              const TU *const *__restrict__ Uring,
+                                              const TX *const *__restrict__ Xring,
+                                              TZ *const *__restrict__ Zring, int64_t n,
+                                              int diag_unit, double *__restrict__ trace_part,
+                                              const DevState *__restrict__ st, int role) {
+    using Cfg = SpmmCfg<TU, CP>;
+    using TA = typename AccumOf<TU>::type;
+    constexpr int NE = Cfg::LANE_ELEMS;
+    if (st && !st->active)
+        return;
+    const int slot_role = st ? st->role[role] : 0;
+    const TX *__restrict__ X = Xring[slot_role];
+    TZ *__restrict__ Z = Zring[slot_role];
+    const TU *__restrict__ U = Uring[slot_role];
+
+    const int tid = threadIdx.x;
+    const int team = tid / Cfg::TEAM, lt = tid % Cfg::TEAM;
+    const int slot = lt / Cfg::GS, sub = lt % Cfg::GS;
+    double trace_acc = 0.0;
+    const int64_t nblocks = (n + Cfg::ROWS_PER_WG - 1) / Cfg::ROWS_PER_WG;
+    for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+        const int64_t row = blk * Cfg::ROWS_PER_WG + team;
+        TA acc[NE];
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            acc[q] = (TA)0;
+        const bool live = row < n;
+        if (live) {
+            const int64_t beg = row_ptr[row], end = row_ptr[row + 1];
+            int64_t e = beg + slot;
+            for (; e + 3 * Cfg::SLOTS < end; e += 4 * Cfg::SLOTS) {
+                int64_t j[4];
+                TA s[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    j[u] = col[e + u * Cfg::SLOTS];
+                    s[u] = (TA)to_f32(val[e + u * Cfg::SLOTS]);
+                }
+                TA g[4][NE];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    GatherLoad<TU, NE>::load(U + j[u] * CP + sub * NE, g[u]);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int q = 0; q < NE; ++q)
+                        acc[q] += s[u] * g[u][q];
+            }
+            for (; e < end; e += Cfg::SLOTS) {
+                const int64_t j = col[e];
+                const TA s = (TA)to_f32(val[e]);
+                TA g[NE];
+                GatherLoad<TU, NE>::load(U + j * CP + sub * NE, g);
+#pragma unroll
+                for (int q = 0; q < NE; ++q)
+                    acc[q] += s * g[q];
+            }
+        }
+        // sum the slots of the team (lanes with the same sub index)
+#pragma unroll
+        for (int off = Cfg::GS; off < Cfg::TEAM; off <<= 1)
+#pragma unroll
+            for (int q = 0; q < NE; ++q) {
+                if constexpr (sizeof(TA) == 8)
+                    acc[q] += shfl_xor_d(acc[q], off);
+                else
+                    acc[q] += shfl_xor_f(acc[q], off);
+            }
+        double d = 0.0;
+        if (live && slot == 0) {
+            TA xi[NE];
+#pragma unroll
+            for (int q = 0; q < NE; ++q)
+                xi[q] = (TA)X[row * CP + sub * NE + q];
+            if (diag_unit)
+#pragma unroll
+                for (int q = 0; q < NE; ++q)
+                    acc[q] += xi[q];
+#pragma unroll
+            for (int q = 0; q < NE; ++q) {
+                Z[row * CP + sub * NE + q] = (TZ)acc[q];
+                d += (double)acc[q] * (double)xi[q];
+            }
+        }
+#pragma unroll
+        for (int off = 1; off < Cfg::GS; off <<= 1)
+            d += shfl_xor_d(d, off);
+        if (live && slot == 0 && sub == 0)
+            trace_acc += d;
+    }
+    __shared__ double sh[256];
+    sh[tid] = trace_acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s)
+            sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0)
+        trace_part[blockIdx.x] = sh[0];
+}
+
+// ---------------------------------------------------------------------------
+// Gram matrix G = U^T U on the matrix cores (the paper's share = X X^T).
+// Each wave walks 16-row tiles; for every output block (a <= b) of 16 x 16
+// it issues four 16x16x4 products over the tile's rows, then adds the tile
+// result into double accumulators.  Wave partials (CPM x CPM, symmetric) go
+// to part[(blockIdx * 4 + wave) * ld].
+// ---------------------------------------------------------------------------
+template <int M> struct SymBlocks {
+    static constexpr int N = M * (M + 1) / 2;
+    __device__ __forceinline__ static void ab(int k, int &a, int &b) {
+        int r = k;
+        a = 0;
+        while (r >= M - a) {
+            r -= M - a;
+            ++a;
+        }
+        b = a + r;
+    }
+};
+
+template <typename T, int CP>
+__global__ __launch_bounds__(256) void k_gram(const T *__restrict__ X, int64_t n,
+                                              double *__restrict__ part, int64_t ld) {
+    constexpr int CPM = CP < 16 ? 16 : CP;
+    constexpr int M = CPM / 16;
+    constexpr int NB = SymBlocks<M>::N;
+    using A4 = typename Acc4<T>::type;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    doublex4 acc64[NB];
+#pragma unroll
+    for (int k = 0; k < NB; ++k)
+        acc64[k] = doublex4{0, 0, 0, 0};
+    const int64_t ntiles = (n + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+        // operand values: component 16a + r of rows 4t + g of the tile
+        T xv[4][M];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t row = tile * 16 + 4 * t + g;
+#pragma unroll
+            for (int a = 0; a < M; ++a) {
+                const int k = 16 * a + r;
+                xv[t][a] = (row < n && k < CP) ? X[row * CP + k] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int kb = 0; kb < NB; ++kb) {
+            int a, b;
+            SymBlocks<M>::ab(kb, a, b);
+            A4 acc = A4{0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+                acc = mfma16x16x4(xv[t][a], xv[t][b], acc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                acc64[kb][q] += (double)acc[q];
+        }
+    }
+    double *out = part + ((int64_t)blockIdx.x * 4 + wave) * ld;
+#pragma unroll
+    for (int kb = 0; kb < NB; ++kb) {
+        int a, b;
+        SymBlocks<M>::ab(kb, a, b);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int i = 16 * a + 4 * g + q, j = 16 * b + r;
+            out[i * CPM + j] = acc64[kb][q];
+            if (a != b)
+                out[j * CPM + i] = acc64[kb][q];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row-wise projection onto the unit simplex for rows spread over four lanes
+// (lanes r, r+16, r+32, r+48 of a wave hold the components of one row).
+// The threshold theta with sum_k max(v_k - theta, 0) = 1 is found by
+// Michelot's finite pivoting: theta = (sum of active v - 1) / #active,
+// drop every active component with v <= theta, repeat until nothing drops.
+// It yields the same threshold as Alg. 1's sort-based search; the sums are
+// carried in double.  The loop is wave-uniform and ends after at most
+// NC * 4 passes.
+// ---------------------------------------------------------------------------
+template <typename T, int NC>
+__device__ __forceinline__ double simplex_threshold(const T (&v)[NC], const bool (&valid)[NC]) {
+    bool act[NC];
+#pragma unroll
+    for (int s = 0; s < NC; ++s)
+        act[s] = valid[s];
+    double theta = 0.0;
+    for (int pass = 0; pass <= 4 * NC; ++pass) {
+        double sum = 0.0;
+        int cnt = 0;
+#pragma unroll
+        for (int s = 0; s < NC; ++s)
+            if (act[s]) {
+                sum += (double)v[s];
+                ++cnt;
+            }
+        sum += shfl_xor_d(sum, 16);
+        sum += shfl_xor_d(sum, 32);
+        cnt += __shfl_xor(cnt, 16, 64);
+        cnt += __shfl_xor(cnt, 32, 64);
+        theta = (sum - 1.0) / (double)(cnt > 0 ? cnt : 1);
+        bool changed = false;
+#pragma unroll
+        for (int s = 0; s < NC; ++s)
+            if (act[s] && (double)v[s] <= theta) {
+                act[s] = false;
+                changed = true;
+            }
+        if (!__any(changed))
+            break;
+    }
+    return theta;
+}
+
+// ---------------------------------------------------------------------------
+// Fused iteration kernel.  Rows are processed in 16-row wave tiles, four
+// waves (64 rows) per workgroup step, in a grid-stride loop.  Lane l of a
+// wave owns row r = l % 16 of the tile and the components
+//   k(s) = 16 (s / 4) + 4 (l / 16) + s % 4,   s = 0 .. 4M-1,
+// which is exactly the layout in which the 16x16x4 product returns
+// (Y G)^T, so Y G needs no data movement: with A = G (rows 16a..) and
+// B = Y^T the contraction index is enumerated through the lanes' own slots.
+//
+// Per row: y = (1+beta) xc - beta xp, sy = (1+beta) zc - beta zp (S Y by
+// linearity from the stored products), grad = -4 (sy - y (G_Y - mu 1 1^T)),
+// v = y - tau grad, p = P_simplex(v), y' = (1+beta') p - beta' xc.
+// The constant mu removed from G_Y changes every gradient row by a
+// multiple of the ones vector, which the projection ignores; it is added
+// back in the line-search sum.  The workgroup then stages p, y' (and
+// p + y, p - y when backtracking) in LDS and each wave accumulates some of
+// the 16 x 16 blocks of their Gram matrices on the matrix cores.
+// ---------------------------------------------------------------------------
+template <typename T, int CP, bool ACCEL, bool BT, bool SHADOW>
+__global__ __launch_bounds__(256) void k_fused(T *const *__restrict__ Xring,
+                                               T *const *__restrict__ Zring,
+                                               __hip_bfloat16 *const *__restrict__ shadow_ring,
+                                               const T *__restrict__ GYs, int64_t n, int c,
+                                               double *__restrict__ part,
+                                               const DevState *__restrict__ st) {
+    constexpr int CPM = CP < 16 ? 16 : CP;
+    constexpr int M = CPM / 16;
+    constexpr int NC = 4 * M;
+    // LDS row stride: float rows are offset by half the banks between the four
+    // row groups an MFMA operand read touches; double rows only need padding
+    constexpr int STRIDE = sizeof(T) == 8 ? CPM + 4 : CPM + (CPM == 16 ? 32 : 16);
+    constexpr int NMAT = 1 + (ACCEL ? 1 : 0) + (BT ? 2 : 0);
+    constexpr int NSYM = SymBlocks<M>::N;
+    constexpr int NBLK = NSYM + (ACCEL ? NSYM : 0) + (BT ? M * M : 0);
+    constexpr int BPW = (NBLK + 3) / 4;  // Gram blocks per wave
+    using A4 = typename Acc4<T>::type;
+    using L = FusedLayout<CPM>;
+
+    if (!st->active)
+        return;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const T *__restrict__ Xc = Xring[st->role[ROLE_C]];
+    const T *__restrict__ Xp = Xring[st->role[ROLE_P]];
+    T *__restrict__ Xn = Xring[st->role[ROLE_N]];
+    const T *__restrict__ Zc = Zring[st->role[ROLE_C]];
+    const T *__restrict__ Zp = Zring[st->role[ROLE_P]];
+    __hip_bfloat16 *shadow = SHADOW ? shadow_ring[st->role[ROLE_N]] : nullptr;
+    const double beta = ACCEL ? st->beta : 0.0;
+    const double beta_next = ACCEL ? st->beta_next : 0.0;
+    const T tau = (T)st->tau;
+    const T b1 = (T)(1.0 + beta), b0 = (T)beta;
+    const T bn1 = (T)(1.0 + beta_next), bn0 = (T)beta_next;
+    const bool use_prev = ACCEL && beta != 0.0;
+
+    // A operands of Y G: G[16a + r][k(s)] for every block a and slot s
+    T gA[M][NC];
+#pragma unroll
+    for (int a = 0; a < M; ++a)
+#pragma unroll
+        for (int s = 0; s < NC; ++s)
+            gA[a][s] = GYs[(16 * a + r) * CPM + 16 * (s >> 2) + 4 * g + (s & 3)];
+
+    __shared__ T lds[NMAT][64 * STRIDE];
+
+    double sc_try = 0.0, sc_lin = 0.0, sc_sq = 0.0, sc_corr = 0.0, sc_bad = 0.0;
+    doublex4 acc64[BPW];
+#pragma unroll
+    for (int k = 0; k < BPW; ++k)
+        acc64[k] = doublex4{0, 0, 0, 0};
+
+    const int64_t nwt = (n + 63) / 64;
+    for (int64_t wt = blockIdx.x; wt < nwt; wt += gridDim.x) {
+        const int64_t row = wt * 64 + wave * 16 + r;
+        const bool live = row < n;
+        T xc[NC], xp[NC], zc[NC], zp[NC];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            const int k0 = 16 * a + 4 * g;
+            const bool ok = live && k0 < CP;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                xc[4 * a + q] = (T)0;
+                zc[4 * a + q] = (T)0;
+                xp[4 * a + q] = (T)0;
+                zp[4 * a + q] = (T)0;
+            }
+            if (ok) {
+                T t4[4];
+                GatherLoad<T, 4>::load(Xc + row * CP + k0, t4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    xc[4 * a + q] = t4[q];
+                GatherLoad<T, 4>::load(Zc + row * CP + k0, t4);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    zc[4 * a + q] = t4[q];
+                if (use_prev) {
+                    GatherLoad<T, 4>::load(Xp + row * CP + k0, t4);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        xp[4 * a + q] = t4[q];
+                    GatherLoad<T, 4>::load(Zp + row * CP + k0, t4);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        zp[4 * a + q] = t4[q];
+                }
+            }
+        }
+        T y[NC], sy[NC];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            y[s] = use_prev ? b1 * xc[s] - b0 * xp[s] : xc[s];
+            sy[s] = use_prev ? b1 * zc[s] - b0 * zp[s] : zc[s];
+        }
+        // Y (G_Y - mu 1 1^T) on the matrix cores, returned in the lane layout of y
+        T yg[NC];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            A4 acc = A4{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < NC; ++s)
+                acc = mfma16x16x4(gA[a][s], y[s], acc);
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                yg[4 * a + q] = acc[q];
+        }
+        T grad[NC], v[NC];
+        bool valid[NC];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int k = 16 * (s >> 2) + 4 * g + (s & 3);
+            valid[s] = live && k < c;
+            grad[s] = (T)(-4) * (sy[s] - yg[s]);
+            v[s] = y[s] - tau * grad[s];
+        }
+        const double theta = simplex_threshold<T, NC>(v, valid);
+        T p[NC];
+        double dsum = 0.0, ysum = 0.0;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const double w = (double)v[s] - theta;
+            p[s] = valid[s] && w > 0.0 ? (T)w : (T)0;
+            if (valid[s]) {
+                const double d = (double)p[s] - (double)y[s];
+                sc_sq += d * d;
+                if (BT) {
+                    sc_try += (double)y[s] * (double)sy[s];
+                    sc_lin += (double)grad[s] * d;
+                    dsum += d;
+                    ysum += (double)y[s];
+                }
+                if (!(v[s] == v[s]) || v[s] - v[s] != (T)0)
+                    sc_bad += 1.0;
+            }
+        }
+        if (BT) {
+            dsum += shfl_xor_d(dsum, 16);
+            dsum += shfl_xor_d(dsum, 32);
+            ysum += shfl_xor_d(ysum, 16);
+            ysum += shfl_xor_d(ysum, 32);
+            if (g == 0 && live)
+                sc_corr += ysum * dsum;
+        }
+        // new iterate (and its bfloat16 copy for the next sparse product)
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            const int k0 = 16 * a + 4 * g;
+            if (live && k0 < CP) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    Xn[row * CP + k0 + q] = p[4 * a + q];
+                if (SHADOW)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        shadow[row * CP + k0 + q] = __float2bfloat16((float)p[4 * a + q]);
+            }
+        }
+        // stage the tile for the Gram products
+        __syncthreads();
+        const int lrow = wave * 16 + r;
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int k = 16 * (s >> 2) + 4 * g + (s & 3);
+            lds[0][lrow * STRIDE + k] = p[s];
+            if constexpr (ACCEL)
+                lds[1][lrow * STRIDE + k] = bn1 * p[s] - bn0 * xc[s];
+            if constexpr (BT) {
+                lds[NMAT - 2][lrow * STRIDE + k] = p[s] + y[s];
+                lds[NMAT - 1][lrow * STRIDE + k] = p[s] - y[s];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < BPW; ++kk) {
+            const int kb = wave + 4 * kk;
+            if (kb < NBLK) {
+                int m1, m2, a, b;
+                if (kb < NSYM) {
+                    m1 = m2 = 0;
+                    SymBlocks<M>::ab(kb, a, b);
+                } else if (ACCEL && kb < 2 * NSYM) {
+                    m1 = m2 = 1;
+                    SymBlocks<M>::ab(kb - NSYM, a, b);
+                } else {
+                    const int q = kb - NSYM - (ACCEL ? NSYM : 0);
+                    m1 = NMAT - 2;
+                    m2 = NMAT - 1;
+                    a = q / M;
+                    b = q % M;
+                }
+                A4 acc = A4{0, 0, 0, 0};
+#pragma unroll
+                for (int t = 0; t < 16; ++t)
+                    acc = mfma16x16x4(lds[m1][(4 * t + g) * STRIDE + 16 * a + r],
+                                      lds[m2][(4 * t + g) * STRIDE + 16 * b + r], acc);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc64[kk][q] += (double)acc[q];
+            }
+        }
+    }
+
+    // write this workgroup's partials
+    double *out = part + (int64_t)blockIdx.x * L::NE;
+#pragma unroll
+    for (int kk = 0; kk < BPW; ++kk) {
+        const int kb = wave + 4 * kk;
+        if (kb < NBLK) {
+            int mat, a, b;
+            bool sym = true;
+            if (kb < NSYM) {
+                mat = 0;
+                SymBlocks<M>::ab(kb, a, b);
+            } else if (ACCEL && kb < 2 * NSYM) {
+                mat = 1;
+                SymBlocks<M>::ab(kb - NSYM, a, b);
+            } else {
+                const int q = kb - NSYM - (ACCEL ? NSYM : 0);
+                mat = 2;
+                sym = false;
+                a = q / M;
+                b = q % M;
+            }
+            double *o = out + mat * L::MAT;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * a + 4 * g + q, j = 16 * b + r;
+                o[i * CPM + j] = acc64[kk][q];
+                if (sym && a != b)
+                    o[j * CPM + i] = acc64[kk][q];
+            }
+        }
+    }
+    // scalars: wave tree, then the four waves in order
+    __shared__ double shs[4][FUSED_NSCAL];
+    double vals[5] = {sc_try, sc_lin, sc_sq, sc_corr, sc_bad};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            vals[k] += shfl_xor_d(vals[k], off);
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+            shs[wave][k] = vals[k];
+    __syncthreads();
+    if (tid < FUSED_NSCAL) {
+        double s = 0.0;
+        if (tid < 5)
+            s = ((shs[0][tid] + shs[1][tid]) + shs[2][tid]) + shs[3][tid];
+        out[3 * L::MAT + tid] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Controller: a single workgroup reads the reduced sums and advances the
+// iteration state (Alg. 4: loss, stop test, inertial parameter; backtracking
+// acceptance).  mode 0: initialisation after Gram + product of Xbar_0;
+// mode 1: after the fused kernel and the product of the trial point.
+// ---------------------------------------------------------------------------
+template <typename T, int CPM>
+__global__ __launch_bounds__(256) void k_control(DevState *__restrict__ st, int mode,
+                                                 const double *__restrict__ red_mats,
+                                                 const double *__restrict__ red_trace,
+                                                 double *__restrict__ GY64,
+                                                 T *__restrict__ GYs,
+                                                 const double *__restrict__ sched,
+                                                 double *__restrict__ hist_f,
+                                                 double *__restrict__ hist_tau,
+                                                 int32_t *__restrict__ hist_trials,
+                                                 double *__restrict__ hist_r) {
+    using L = FusedLayout<CPM>;
+    __shared__ double sh[256];
+    __shared__ int decision;
+    const int tid = threadIdx.x;
+    if (mode == 1 && !st->active)
+        return;
+    const int c = st->c;
+    const double *Gp = red_mats;                       // Gram of the new point
+    const double *Gnext = red_mats + (mode == 1 && st->accelerate ? L::MAT : 0);
+    const double *Mx = red_mats + 2 * L::MAT;
+    const double *sc = red_mats + 3 * L::MAT;
+
+    // ||G_p||^2 and (backtracking) <M, G_p + G_Y>, fixed-order tree sums
+    double a_sq = 0.0, a_m = 0.0;
+    for (int e = tid; e < CPM * CPM; e += 256) {
+        a_sq += Gp[e] * Gp[e];
+        if (mode == 1 && st->backtrack)
+            a_m += Mx[e] * (Gp[e] + GY64[e]);
+    }
+    sh[tid] = a_sq;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s)
+            sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    const double gp_sq = sh[0];
+    __syncthreads();
+    sh[tid] = a_m;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s)
+            sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    const double m_dot = sh[0];
+    __syncthreads();
+
+    if (tid == 0) {
+        const double tr_p = red_trace[0];
+        const double f_p = st->s2 + gp_sq - 2.0 * tr_p;
+        int accept = 1;
+        if (mode == 0) {
+            st->f = f_p;
+            st->f_prev = f_p;
+            st->iter = 0;
+            st->trials = 0;
+            st->trial_in_iter = 1;
+            if (hist_f)
+                hist_f[0] = f_p;
+            if (!(f_p == f_p) || f_p - f_p != 0.0) {
+                st->error = ERR_NONFINITE;
+                st->stop_reason = STOP_ERROR;
+                st->active = 0;
+                accept = 0;
+            }
+        } else {
+            const double tr_y = sc[FS_TRY], lin_s = sc[FS_LIN], sq = sc[FS_SQ];
+            const double corr = sc[FS_CORR], bad = sc[FS_BAD];
+            st->trials += 1;
+            const bool finite = (f_p == f_p) && (f_p - f_p == 0.0) && bad == 0.0;
+            if (!finite) {
+                st->error = ERR_NONFINITE;
+                st->stop_reason = STOP_ERROR;
+                st->active = 0;
+                accept = 0;
+            } else if (st->backtrack) {
+                const double lin = lin_s + 4.0 * st->mu * corr;
+                const double df = m_dot - 2.0 * (tr_p - tr_y);
+                const double rhs = lin + 0.5 * st->L * sq;
+                st->tr_y_last = tr_y;
+                st->df_last = df;
+                st->rhs_last = rhs;
+                accept = df <= rhs;
+            }
+            if (st->active && accept) {
+                const int it = st->iter + 1;
+                const double rr = sqrt(sq) / st->tau;
+                st->iter = it;
+                st->f_prev = st->f;
+                st->f = f_p;
+                st->r = rr;
+                if (it == 1)
+                    st->r1 = rr;
+                if (it < st->hist_cap) {
+                    if (hist_f) hist_f[it] = f_p;
+                    if (hist_tau) hist_tau[it] = st->tau;
+                    if (hist_trials) hist_trials[it] = st->trial_in_iter;
+                    if (hist_r) hist_r[it] = rr;
+                }
+                // ring: trial -> current, current -> previous, previous -> next trial
+                const int rc = st->role[ROLE_C], rp = st->role[ROLE_P], rn = st->role[ROLE_N];
+                st->role[ROLE_C] = rn;
+                st->role[ROLE_P] = rc;
+                st->role[ROLE_N] = rp;
+                // inertial parameter (Alg. 4)
+                const double t_next = 0.5 * (1.0 + sqrt(1.0 + 4.0 * st->t * st->t));
+                st->beta = st->beta_next;
+                st->t = t_next;
+                if (st->accelerate) {
+                    const double t_after = 0.5 * (1.0 + sqrt(1.0 + 4.0 * t_next * t_next));
+                    st->beta_next = (t_next - 1.0) / t_after;
+                } else {
+                    st->beta_next = 0.0;
+                }
+                st->trial_in_iter = 1;
+                // stop tests
+                if (st->tol_loss == st->tol_loss && st->f_prev - st->f <= st->tol_loss) {
+                    st->stop_reason = STOP_LOSS;
+                    st->active = 0;
+                } else if (st->tol_pgrad > 0.0 && rr <= st->tol_pgrad * st->r1) {
+                    st->stop_reason = STOP_PGRAD;
+                    st->active = 0;
+                } else if (it >= st->max_iter) {
+                    st->stop_reason = STOP_MAXITER;
+                    st->active = 0;
+                }
+                if (it >= st->target)
+                    st->active = 0;
+                // step of the next iteration
+                if (!st->backtrack) {
+                    if (sched) {
+                        const int k = it < st->sched_len ? it : st->sched_len - 1;
+                        st->tau = sched[k];
+                    } else {
+                        st->tau = st->tau0;
+                    }
+                    st->L = 1.0 / st->tau;
+                }
+            } else if (st->active) {
+                st->trial_in_iter += 1;
+                st->L *= st->eta;
+                st->tau = 1.0 / st->L;
+                if (!(st->L < 1e300) || st->trial_in_iter > 1000) {
+                    st->error = ERR_STEP;
+                    st->stop_reason = STOP_ERROR;
+                    st->active = 0;
+                }
+                accept = 0;
+            }
+        }
+        decision = accept;
+    }
+    __syncthreads();
+    if (!decision)
+        return;
+    // G of the next extrapolated point: keep it in double and hand the fused
+    // kernel a copy with its mean over the c x c block removed.
+    double msum = 0.0;
+    for (int e = tid; e < CPM * CPM; e += 256) {
+        const int i = e / CPM, j = e % CPM;
+        if (i < c && j < c)
+            msum += Gnext[e];
+    }
+    sh[tid] = msum;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s)
+            sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    const double mu = sh[0] / ((double)c * (double)c);
+    for (int e = tid; e < CPM * CPM; e += 256) {
+        const int i = e / CPM, j = e % CPM;
+        const double gv = Gnext[e];
+        GY64[e] = gv;
+        GYs[e] = (i < c && j < c) ? (T)(gv - mu) : (T)0;
+    }
+    if (tid == 0)
+        st->mu = mu;
+}
+
+// ---------------------------------------------------------------------------
+// Power iteration for ||S_eff||_2: w = S_eff v (double), partial sums of
+// w_i^2; then v = w / ||w|| once the host-visible estimate is recorded.
+// ---------------------------------------------------------------------------
+template <typename VS>
+__global__ __launch_bounds__(256) void k_spmv_power(const int64_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col,
+                                                    const VS *__restrict__ val,
+                                                    const double *__restrict__ v,
+                                                    double *__restrict__ w, int64_t n, int diag_unit,
+                                                    double *__restrict__ part) {
+    __shared__ double sh[256];
+    const int tid = threadIdx.x, lane8 = tid & 7, row_in = tid >> 3;
+    double acc_sq = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * 32; base < n; base += (int64_t)gridDim.x * 32) {
+        const int64_t i = base + row_in;
+        double acc = 0.0;
+        if (i < n) {
+            for (int64_t e = row_ptr[i] + lane8; e < row_ptr[i + 1]; e += 8)
+                acc += (double)to_f32(val[e]) * v[col[e]];
+        }
+        for (int off = 1; off < 8; off <<= 1)
+            acc += shfl_xor_d(acc, off);
+        if (i < n && lane8 == 0) {
+            if (diag_unit)
+                acc += v[i];
+            w[i] = acc;
+            acc_sq += acc * acc;
+        }
+    }
+    sh[tid] = acc_sq;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s)
+            sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0)
+        part[blockIdx.x] = sh[0];
+}
+template <>
+__global__ __launch_bounds__(256) void k_spmv_power<double>(const int64_t *__restrict__ row_ptr,
+                                                            const int32_t *__restrict__ col,
+                                                            const double *__restrict__ val,
+                                                            const double *__restrict__ v,
+                                                            double *__restrict__ w, int64_t n,
+                                                            int diag_unit,
+                                                            double *__restrict__ part) {
+    __shared__ double sh[256];
+    const int tid = threadIdx.x, lane8 = tid & 7, row_in = tid >> 3;
+    double acc_sq = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * 32; base < n; base += (int64_t)gridDim.x * 32) {
+        const int64_t i = base + row_in;
+        double acc = 0.0;
+        if (i < n) {
+            for (int64_t e = row_ptr[i] + lane8; e < row_ptr[i + 1]; e += 8)
+                acc += val[e] * v[col[e]];
+        }
+        for (int off = 1; off < 8; off <<= 1)
+            acc += shfl_xor_d(acc, off);
+        if (i < n && lane8 == 0) {
+            if (diag_unit)
+                acc += v[i];
+            w[i] = acc;
+            acc_sq += acc * acc;
+        }
+    }
+    sh[tid] = acc_sq;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s)
+            sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0)
+        part[blockIdx.x] = sh[0];
+}
+
+// est[it] = ||w||; flag[0] = 1 once |est - prev| <= rtol est.
+__global__ void k_power_update(const double *__restrict__ sumsq, double *__restrict__ est, int it,
+                               double rtol, int32_t *__restrict__ flag) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        const double e = sqrt(sumsq[0]);
+        est[it] = e;
+        if (e == 0.0 || (it > 0 && fabs(e - est[it - 1]) <= rtol * e))
+            flag[0] = 1;
+    }
+}
+
+__global__ void k_power_scale(const double *__restrict__ w, double *__restrict__ v, int64_t n,
+                              const double *__restrict__ est, int it,
+                              const int32_t *__restrict__ flag) {
+    if (flag[0])
+        return;
+    const double inv = 1.0 / est[it];
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = w[i] * inv;
+}
+
+__global__ void k_fill(double *__restrict__ v, int64_t n, double value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        v[i] = value;
+}
+
+// ---------------------------------------------------------------------------
+// Standalone row-wise projection onto the unit simplex (any leading
+// dimension), four lanes per row as in the fused kernel.
+// ---------------------------------------------------------------------------
+template <typename T, int CPM>
+__global__ __launch_bounds__(256) void k_project(const T *__restrict__ V, T *__restrict__ out,
+                                                 int64_t rows, int c, int64_t ld) {
+    constexpr int NC = CPM / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const int64_t ntiles = (rows + 15) / 16;
+    for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < ntiles; tile += (int64_t)gridDim.x * 4) {
+        const int64_t row = tile * 16 + r;
+        T v[NC];
+        bool valid[NC];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int k = 16 * (s >> 2) + 4 * g + (s & 3);
+            valid[s] = row < rows && k < c;
+            v[s] = valid[s] ? V[row * ld + k] : (T)0;
+        }
+        const double theta = simplex_threshold<T, NC>(v, valid);
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int k = 16 * (s >> 2) + 4 * g + (s & 3);
+            if (valid[s]) {
+                const double w = (double)v[s] - theta;
+                out[row * ld + k] = w > 0.0 ? (T)w : (T)0;
+            }
+        }
+    }
+}
+
+}  // namespace fc

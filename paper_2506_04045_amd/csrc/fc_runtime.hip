@@ -1,0 +1,1120 @@
+// fc_runtime.hip -- host runtime and C ABI of the gfx950 fuzzy-clustering
+// solver (see include/fc.h for the contract of every entry point).
+//
+// A solver owns, on one GPU:
+//   * a ring of three n x CP iterate buffers (Xbar_c, Xbar_p, trial) and the
+//     three matching products S Xbar, so the extrapolated point and S Y are
+//     formed inside the fused kernel from stored rows (S is applied once per
+//     trial, to the trial point, whose product is reused by the next step);
+//   * in mixed precision a half copy of the values of S and a bfloat16
+//     shadow of every iterate, which is what the sparse product gathers;
+//   * per-workgroup partial sums, their reductions, the device state and the
+//     per-iteration history.
+// One trial = k_fused -> k_spmm -> two fixed-order reductions -> k_control;
+// the host only re-launches that sequence and reads the state back.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/fc.h"
+#include "fc_kernels.hpp"
+
+using namespace fc;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fc_status fail(fc_status s, const std::string &msg) {
+    g_last_error = msg;
+    return s;
+}
+
+#define HIPCHK(expr)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(FC_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int cp_of(int c) {
+    int cp = 4;
+    while (cp < c)
+        cp <<= 1;
+    return cp;
+}
+int cpm_of(int cp) { return cp < 16 ? 16 : cp; }
+
+int device_cus() {
+    int dev = 0, cus = 0;
+    if (hipGetDevice(&dev) != hipSuccess)
+        return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+        return 256;
+    return cus;
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+int grid_1d(int64_t work, int64_t per_block, int64_t cap) {
+    int64_t g = cdiv(work, per_block);
+    if (g < 1)
+        g = 1;
+    if (g > cap)
+        g = cap;
+    return (int)g;
+}
+
+size_t dtype_size(fc_dtype d) {
+    switch (d) {
+    case FC_F64: return 8;
+    case FC_F32: return 4;
+    case FC_F16: return 2;
+    case FC_BF16: return 2;
+    }
+    return 0;
+}
+
+// RAII for temporary device buffers of the stateless entry points.
+struct DevBuf {
+    void *p = nullptr;
+    hipStream_t s = nullptr;
+    ~DevBuf() {
+        if (p)
+            (void)hipFreeAsync(p, s);
+    }
+};
+
+hipError_t dev_alloc(DevBuf &b, size_t bytes, hipStream_t s) {
+    b.s = s;
+    return hipMallocAsync(&b.p, bytes > 0 ? bytes : 16, s);
+}
+
+// Reduction launch: out[e] = sum over np partial rows of in (row stride ld).
+void launch_reduce(const double *in, int64_t np, int64_t ld, int64_t ne, double *out,
+                   hipStream_t s) {
+    const int eb = ne >= 64 ? 64 : (ne >= 16 ? 16 : 1);
+    const int blocks = (int)cdiv(ne, eb);
+    hipLaunchKernelGGL(k_reduce_cols, dim3(blocks), dim3(256), 0, s, in, np, ld, ne, out, eb);
+}
+
+// Dispatch a functor on the padded width CP in {4, 8, 16, 32, 64}.
+template <typename F> fc_status with_cp(int cp, F &&f) {
+    switch (cp) {
+    case 4: return f(std::integral_constant<int, 4>());
+    case 8: return f(std::integral_constant<int, 8>());
+    case 16: return f(std::integral_constant<int, 16>());
+    case 32: return f(std::integral_constant<int, 32>());
+    case 64: return f(std::integral_constant<int, 64>());
+    }
+    return fail(FC_ERR_UNSUPPORTED, "padded width out of range");
+}
+
+fc_status check_csr_args(const fc_csr *S) {
+    if (!S)
+        return fail(FC_ERR_INVALID_ARG, "S is NULL");
+    if (S->n < 1 || S->n > INT32_MAX)
+        return fail(FC_ERR_INVALID_ARG, "S->n must be in [1, 2^31 - 1]");
+    if (S->nnz < 0)
+        return fail(FC_ERR_INVALID_ARG, "S->nnz < 0");
+    if (!S->row_ptr || (S->nnz > 0 && (!S->col_idx || !S->values)))
+        return fail(FC_ERR_INVALID_ARG, "S arrays are NULL");
+    if (S->values_dtype != FC_F64 && S->values_dtype != FC_F32 && S->values_dtype != FC_F16)
+        return fail(FC_ERR_INVALID_ARG, "S values must be FC_F64, FC_F32 or FC_F16");
+    return FC_OK;
+}
+
+// ||S||_F^2 of the stored values, summed on the device in double.
+fc_status sum_squares(const fc_csr *S, hipStream_t s, double *out) {
+    const int g = grid_1d(S->nnz, 256 * 8, 4096);
+    DevBuf part, red;
+    HIPCHK(dev_alloc(part, sizeof(double) * g, s));
+    HIPCHK(dev_alloc(red, sizeof(double), s));
+    switch (S->values_dtype) {
+    case FC_F64:
+        hipLaunchKernelGGL(k_sumsq<double>, dim3(g), dim3(256), 0, s, (const double *)S->values,
+                           S->nnz, (double *)part.p);
+        break;
+    case FC_F32:
+        hipLaunchKernelGGL(k_sumsq<float>, dim3(g), dim3(256), 0, s, (const float *)S->values,
+                           S->nnz, (double *)part.p);
+        break;
+    default:
+        hipLaunchKernelGGL(k_sumsq<__half>, dim3(g), dim3(256), 0, s, (const __half *)S->values,
+                           S->nnz, (double *)part.p);
+        break;
+    }
+    HIPCHK(hipGetLastError());
+    launch_reduce((const double *)part.p, g, 1, 1, (double *)red.p, s);
+    HIPCHK(hipMemcpyAsync(out, red.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return FC_OK;
+}
+
+// Power iteration for ||S_eff||_2 from the normalised ones vector.
+fc_status power_norm(const fc_csr *S, int diag_unit, int max_iter, double rtol, hipStream_t s,
+                     double *norm_out, int32_t *iters_out) {
+    const int64_t n = S->n;
+    if (max_iter < 1)
+        max_iter = 1;
+    const int g = grid_1d(n, 32, 8192);
+    DevBuf v, w, part, red, est, flag;
+    HIPCHK(dev_alloc(v, sizeof(double) * n, s));
+    HIPCHK(dev_alloc(w, sizeof(double) * n, s));
+    HIPCHK(dev_alloc(part, sizeof(double) * g, s));
+    HIPCHK(dev_alloc(red, sizeof(double), s));
+    HIPCHK(dev_alloc(est, sizeof(double) * (max_iter + 1), s));
+    HIPCHK(dev_alloc(flag, sizeof(int32_t), s));
+    HIPCHK(hipMemsetAsync(flag.p, 0, sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_fill, dim3(grid_1d(n, 256, 4096)), dim3(256), 0, s, (double *)v.p, n,
+                       1.0 / std::sqrt((double)n));
+    int it = 0;
+    int32_t done = 0;
+    for (it = 0; it < max_iter && !done; ++it) {
+        switch (S->values_dtype) {
+        case FC_F64:
+            hipLaunchKernelGGL(k_spmv_power<double>, dim3(g), dim3(256), 0, s, S->row_ptr,
+                               S->col_idx, (const double *)S->values, (const double *)v.p,
+                               (double *)w.p, n, diag_unit, (double *)part.p);
+            break;
+        case FC_F32:
+            hipLaunchKernelGGL(k_spmv_power<float>, dim3(g), dim3(256), 0, s, S->row_ptr,
+                               S->col_idx, (const float *)S->values, (const double *)v.p,
+                               (double *)w.p, n, diag_unit, (double *)part.p);
+            break;
+        default:
+            hipLaunchKernelGGL(k_spmv_power<__half>, dim3(g), dim3(256), 0, s, S->row_ptr,
+                               S->col_idx, (const __half *)S->values, (const double *)v.p,
+                               (double *)w.p, n, diag_unit, (double *)part.p);
+            break;
+        }
+        launch_reduce((const double *)part.p, g, 1, 1, (double *)red.p, s);
+        hipLaunchKernelGGL(k_power_update, dim3(1), dim3(64), 0, s, (const double *)red.p,
+                           (double *)est.p, it, rtol, (int32_t *)flag.p);
+        hipLaunchKernelGGL(k_power_scale, dim3(grid_1d(n, 256, 4096)), dim3(256), 0, s,
+                           (const double *)w.p, (double *)v.p, n, (const double *)est.p, it,
+                           (const int32_t *)flag.p);
+        if ((it + 1) % 16 == 0 || it + 1 == max_iter) {
+            HIPCHK(hipMemcpyAsync(&done, flag.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+    }
+    HIPCHK(hipGetLastError());
+    // the last recorded estimate is est[k] with k = first converged index or it - 1
+    std::vector<double> h(it);
+    HIPCHK(hipMemcpyAsync(h.data(), est.p, sizeof(double) * it, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int k = it - 1;
+    for (int q = 1; q < it; ++q)
+        if (h[q] == 0.0 || std::fabs(h[q] - h[q - 1]) <= rtol * h[q]) {
+            k = q;
+            break;
+        }
+    *norm_out = h[k];
+    if (iters_out)
+        *iters_out = k + 1;
+    return FC_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// solver object
+// ---------------------------------------------------------------------------
+struct fc_solver {
+    int64_t n = 0, nnz = 0;
+    int c = 0, cp = 0, cpm = 0;
+    fc_precision prec = FC_PREC_FP32;
+    fc_diag diag = FC_DIAG_UNIT;
+    int accelerate = 1;
+    int backtrack = 0;
+    const int64_t *row_ptr = nullptr;
+    const int32_t *col = nullptr;
+    const void *val = nullptr;  // values used by the kernels (maybe owned)
+    fc_dtype vdt = FC_F32;
+    void *val_owned = nullptr;
+    hipStream_t stream = nullptr;
+    void *X[3] = {nullptr, nullptr, nullptr};
+    void *Z[3] = {nullptr, nullptr, nullptr};
+    void *shadow[3] = {nullptr, nullptr, nullptr};
+    void **d_Xring = nullptr, **d_Zring = nullptr, **d_Sring = nullptr;
+    DevState *d_state = nullptr;
+    DevState h = {};
+    double *d_GY64 = nullptr;
+    void *d_GYs = nullptr;
+    double *d_part_fused = nullptr, *d_part_spmm = nullptr, *d_part_gram = nullptr;
+    int g_fused = 1, g_spmm = 1, g_gram = 1;
+    double *d_red_mats = nullptr, *d_red_trace = nullptr;
+    double *d_sched = nullptr;
+    int sched_len = 0;
+    double *d_hist_f = nullptr, *d_hist_tau = nullptr, *d_hist_r = nullptr;
+    int32_t *d_hist_trials = nullptr;
+    int hist_cap = 65536;
+    int check_every = 16;
+    int max_iter = 100;
+    double spec_norm = 0.0, L_thm = 0.0;
+    std::vector<void *> allocs;
+
+    ~fc_solver() {
+        for (void *p : allocs)
+            (void)hipFree(p);
+    }
+    template <typename P> hipError_t alloc(P **p, size_t bytes) {
+        void *q = nullptr;
+        hipError_t e = hipMalloc(&q, bytes > 0 ? bytes : 16);
+        if (e == hipSuccess) {
+            allocs.push_back(q);
+            *p = (P *)q;
+        }
+        return e;
+    }
+};
+
+namespace {
+
+int fused_ne(int cpm) { return 3 * cpm * cpm + FUSED_NSCAL; }
+
+// Launch one trial: fused step -> sparse product of the trial point ->
+// reductions -> controller.
+template <typename T, typename TU, typename VS, int CP>
+fc_status launch_trial_t(fc_solver *h) {
+    constexpr int CPM = CP < 16 ? 16 : CP;
+    using Cfg = SpmmCfg<TU, CP>;
+    hipStream_t s = h->stream;
+    const bool shadow = h->prec == FC_PREC_MIXED;
+    auto Xr = (T *const *)h->d_Xring;
+    auto Zr = (T *const *)h->d_Zring;
+    auto Sr = (__hip_bfloat16 *const *)h->d_Sring;
+    auto GYs = (const T *)h->d_GYs;
+#define FUSED_LAUNCH(A, B, SH)                                                                 \
+    hipLaunchKernelGGL((k_fused<T, CP, A, B, SH>), dim3(h->g_fused), dim3(256), 0, s, Xr, Zr, Sr, \
+                       GYs, h->n, h->c, h->d_part_fused, (const DevState *)h->d_state)
+    if constexpr (std::is_same<T, float>::value) {
+        if (shadow) {
+            if (h->accelerate && h->backtrack) FUSED_LAUNCH(true, true, true);
+            else if (h->accelerate) FUSED_LAUNCH(true, false, true);
+            else if (h->backtrack) FUSED_LAUNCH(false, true, true);
+            else FUSED_LAUNCH(false, false, true);
+        } else {
+            if (h->accelerate && h->backtrack) FUSED_LAUNCH(true, true, false);
+            else if (h->accelerate) FUSED_LAUNCH(true, false, false);
+            else if (h->backtrack) FUSED_LAUNCH(false, true, false);
+            else FUSED_LAUNCH(false, false, false);
+        }
+    } else {
+        if (h->accelerate && h->backtrack) FUSED_LAUNCH(true, true, false);
+        else if (h->accelerate) FUSED_LAUNCH(true, false, false);
+        else if (h->backtrack) FUSED_LAUNCH(false, true, false);
+        else FUSED_LAUNCH(false, false, false);
+    }
+#undef FUSED_LAUNCH
+    const TU *const *Ur = shadow ? (const TU *const *)h->d_Sring : (const TU *const *)h->d_Xring;
+    hipLaunchKernelGGL((k_spmm<TU, T, T, VS, CP>), dim3(h->g_spmm), dim3(256), 0, s, h->row_ptr,
+                       h->col, (const VS *)h->val, Ur, (const T *const *)h->d_Xring, Zr, h->n,
+                       (int)(h->diag == FC_DIAG_UNIT), h->d_part_spmm,
+                       (const DevState *)h->d_state, (int)ROLE_N);
+    const int ne = fused_ne(CPM);
+    launch_reduce(h->d_part_fused, h->g_fused, ne, ne, h->d_red_mats, s);
+    launch_reduce(h->d_part_spmm, h->g_spmm, 1, 1, h->d_red_trace, s);
+    hipLaunchKernelGGL((k_control<T, CPM>), dim3(1), dim3(256), 0, s, h->d_state, 1,
+                       (const double *)h->d_red_mats, (const double *)h->d_red_trace, h->d_GY64,
+                       (T *)h->d_GYs, (const double *)h->d_sched, h->d_hist_f, h->d_hist_tau,
+                       h->d_hist_trials, h->d_hist_r);
+    (void)Cfg::TEAM;
+    HIPCHK(hipGetLastError());
+    return FC_OK;
+}
+
+// Initial evaluation: Gram and product of Xbar_0, then the controller.
+template <typename T, typename TU, typename VS, int CP>
+fc_status launch_init_t(fc_solver *h) {
+    constexpr int CPM = CP < 16 ? 16 : CP;
+    hipStream_t s = h->stream;
+    const bool shadow = h->prec == FC_PREC_MIXED;
+    const int ld = CPM * CPM;
+    hipLaunchKernelGGL((k_gram<T, CP>), dim3(h->g_gram), dim3(256), 0, s, (const T *)h->X[0],
+                       h->n, h->d_part_gram, (int64_t)ld);
+    if (shadow)
+        hipLaunchKernelGGL((k_convert<float, __hip_bfloat16>), dim3(grid_1d(h->n * h->cp, 256, 8192)),
+                           dim3(256), 0, s, (const float *)h->X[0], (__hip_bfloat16 *)h->shadow[0],
+                           h->n * h->cp);
+    const TU *const *Ur = shadow ? (const TU *const *)h->d_Sring : (const TU *const *)h->d_Xring;
+    hipLaunchKernelGGL((k_spmm<TU, T, T, VS, CP>), dim3(h->g_spmm), dim3(256), 0, s, h->row_ptr,
+                       h->col, (const VS *)h->val, Ur, (const T *const *)h->d_Xring,
+                       (T *const *)h->d_Zring, h->n, (int)(h->diag == FC_DIAG_UNIT),
+                       h->d_part_spmm, (const DevState *)h->d_state, (int)ROLE_C);
+    launch_reduce(h->d_part_gram, (int64_t)h->g_gram * 4, ld, ld, h->d_red_mats, s);
+    launch_reduce(h->d_part_spmm, h->g_spmm, 1, 1, h->d_red_trace, s);
+    hipLaunchKernelGGL((k_control<T, CPM>), dim3(1), dim3(256), 0, s, h->d_state, 0,
+                       (const double *)h->d_red_mats, (const double *)h->d_red_trace, h->d_GY64,
+                       (T *)h->d_GYs, (const double *)h->d_sched, h->d_hist_f, h->d_hist_tau,
+                       h->d_hist_trials, h->d_hist_r);
+    HIPCHK(hipGetLastError());
+    return FC_OK;
+}
+
+fc_status launch_trial(fc_solver *h) {
+    return with_cp(h->cp, [&](auto cpc) -> fc_status {
+        constexpr int CP = decltype(cpc)::value;
+        if (h->prec == FC_PREC_FP64)
+            return launch_trial_t<double, double, double, CP>(h);
+        if (h->prec == FC_PREC_FP32)
+            return launch_trial_t<float, float, float, CP>(h);
+        if constexpr (CP >= 8)
+            return launch_trial_t<float, __hip_bfloat16, __half, CP>(h);
+        return fail(FC_ERR_UNSUPPORTED, "mixed precision needs c >= 5 (padded width >= 8)");
+    });
+}
+
+fc_status launch_init(fc_solver *h) {
+    return with_cp(h->cp, [&](auto cpc) -> fc_status {
+        constexpr int CP = decltype(cpc)::value;
+        if (h->prec == FC_PREC_FP64)
+            return launch_init_t<double, double, double, CP>(h);
+        if (h->prec == FC_PREC_FP32)
+            return launch_init_t<float, float, float, CP>(h);
+        if constexpr (CP >= 8)
+            return launch_init_t<float, __hip_bfloat16, __half, CP>(h);
+        return fail(FC_ERR_UNSUPPORTED, "mixed precision needs c >= 5 (padded width >= 8)");
+    });
+}
+
+fc_status read_state(fc_solver *h) {
+    HIPCHK(hipMemcpyAsync(&h->h, h->d_state, sizeof(DevState), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return FC_OK;
+}
+
+fc_status write_state(fc_solver *h) {
+    HIPCHK(hipMemcpyAsync(h->d_state, &h->h, sizeof(DevState), hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return FC_OK;
+}
+
+void fill_info(const fc_solver *h, fc_info *info) {
+    if (!info)
+        return;
+    info->iter = h->h.iter;
+    info->trials = h->h.trials;
+    info->stop_reason = h->h.stop_reason;
+    info->reserved = 0;
+    info->f = h->h.f;
+    info->f_prev = h->h.f_prev;
+    info->L = h->h.iter > 0 || h->backtrack ? h->h.L : 1.0 / h->h.tau;
+    info->t = h->h.t;
+    info->beta = h->h.beta_next;
+    info->pgrad = h->h.r;
+    info->pgrad_rel = h->h.r1 > 0.0 ? h->h.r / h->h.r1 : 0.0;
+}
+
+fc_status status_of(const fc_solver *h) {
+    if (h->h.error == ERR_NONFINITE)
+        return fail(FC_ERR_NONFINITE, "the objective or an iterate became non-finite");
+    if (h->h.error == ERR_STEP)
+        return fail(FC_ERR_STEP, "backtracking found no acceptable step (L overflow or 1000 trials)");
+    return FC_OK;
+}
+
+// Run until `target` accepted iterations (or a stop) with the given budget.
+fc_status run_until(fc_solver *h, int32_t target, int32_t max_iter) {
+    if (h->h.error != ERR_NONE)
+        return status_of(h);
+    h->h.target = target;
+    h->h.max_iter = max_iter;
+    h->h.active = h->h.iter < target && h->h.iter < max_iter ? 1 : 0;
+    if (h->h.active)
+        h->h.stop_reason = STOP_NONE;
+    fc_status st = write_state(h);
+    if (st != FC_OK)
+        return st;
+    while (h->h.active) {
+        int launches = h->backtrack ? h->check_every : (target - h->h.iter);
+        if (launches < 1)
+            launches = 1;
+        for (int k = 0; k < launches; ++k) {
+            st = launch_trial(h);
+            if (st != FC_OK)
+                return st;
+        }
+        st = read_state(h);
+        if (st != FC_OK)
+            return st;
+    }
+    return status_of(h);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void fc_options_default(fc_options *opt) {
+    if (!opt)
+        return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->struct_size = sizeof(fc_options);
+    opt->c = 0;
+    opt->precision = FC_PREC_FP32;
+    opt->diag = FC_DIAG_UNIT;
+    opt->accelerate = 1;
+    opt->step_rule = FC_STEP_FIXED;
+    opt->step = 0.0;
+    opt->L0 = 0.0;
+    opt->eta = 2.0;
+    opt->max_iter = 100;
+    opt->check_every = 16;
+    opt->tol_loss = std::nan("");
+    opt->tol_pgrad = 0.0;
+    opt->validate = 0;
+    opt->step_schedule = nullptr;
+    opt->step_schedule_len = 0;
+}
+
+const char *fc_last_error(void) { return g_last_error.c_str(); }
+
+fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_dtype u0_dtype,
+                    void *stream, fc_solver **out) {
+    g_last_error.clear();
+    if (!out)
+        return fail(FC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    fc_status st = check_csr_args(S);
+    if (st != FC_OK)
+        return st;
+    if (!opt || opt->struct_size != sizeof(fc_options))
+        return fail(FC_ERR_INVALID_ARG, "options missing or struct_size mismatch (call fc_options_default)");
+    if (opt->c < 1 || opt->c > 64)
+        return fail(FC_ERR_INVALID_ARG, "c must be in [1, 64]");
+    if (opt->precision != FC_PREC_FP64 && opt->precision != FC_PREC_FP32 &&
+        opt->precision != FC_PREC_MIXED)
+        return fail(FC_ERR_INVALID_ARG, "unknown precision");
+    if (opt->diag != FC_DIAG_STORED && opt->diag != FC_DIAG_UNIT)
+        return fail(FC_ERR_INVALID_ARG, "unknown diagonal mode");
+    if (opt->step_rule != FC_STEP_FIXED && opt->step_rule != FC_STEP_BACKTRACK)
+        return fail(FC_ERR_INVALID_ARG, "unknown step rule");
+    if (opt->step_rule == FC_STEP_BACKTRACK && !(opt->eta > 1.0))
+        return fail(FC_ERR_INVALID_ARG, "eta must be > 1");
+    if (opt->max_iter < 0)
+        return fail(FC_ERR_INVALID_ARG, "max_iter < 0");
+    if (opt->step_schedule && opt->step_schedule_len < 1)
+        return fail(FC_ERR_INVALID_ARG, "step_schedule_len must be >= 1");
+    if (U0 && u0_dtype != FC_F64 && u0_dtype != FC_F32)
+        return fail(FC_ERR_INVALID_ARG, "U0 must be FC_F64 or FC_F32");
+    if (opt->precision == FC_PREC_FP64 && S->values_dtype != FC_F64)
+        return fail(FC_ERR_INVALID_ARG, "FP64 precision needs FC_F64 values");
+    if (opt->precision == FC_PREC_FP32 && S->values_dtype != FC_F32)
+        return fail(FC_ERR_INVALID_ARG, "FP32 precision needs FC_F32 values");
+    if (opt->precision == FC_PREC_MIXED && S->values_dtype == FC_F64)
+        return fail(FC_ERR_INVALID_ARG, "mixed precision needs FC_F32 or FC_F16 values");
+    if (opt->precision == FC_PREC_MIXED && cp_of(opt->c) < 8)
+        return fail(FC_ERR_UNSUPPORTED, "mixed precision needs c >= 5");
+
+    fc_solver *h = new (std::nothrow) fc_solver();
+    if (!h)
+        return fail(FC_ERR_OUT_OF_MEMORY, "host allocation failed");
+    auto cleanup = [&](fc_status s) {
+        delete h;
+        return s;
+    };
+    h->n = S->n;
+    h->nnz = S->nnz;
+    h->c = opt->c;
+    h->cp = cp_of(opt->c);
+    h->cpm = cpm_of(h->cp);
+    h->prec = opt->precision;
+    h->diag = opt->diag;
+    h->accelerate = opt->accelerate ? 1 : 0;
+    h->backtrack = opt->step_rule == FC_STEP_BACKTRACK ? 1 : 0;
+    h->row_ptr = S->row_ptr;
+    h->col = S->col_idx;
+    h->val = S->values;
+    h->vdt = S->values_dtype;
+    h->stream = (hipStream_t)stream;
+    h->check_every = opt->check_every > 0 ? opt->check_every : 16;
+    h->max_iter = opt->max_iter;
+    hipStream_t s = h->stream;
+
+    if (opt->validate) {
+        int32_t *flags = nullptr;
+        if (hipMalloc(&flags, sizeof(int32_t)) != hipSuccess)
+            return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "validation buffer"));
+        h->allocs.push_back(flags);
+        if (hipMemsetAsync(flags, 0, sizeof(int32_t), s) != hipSuccess)
+            return cleanup(fail(FC_ERR_DEVICE, "memset"));
+        const int g = grid_1d(S->n, 256, 8192);
+        if (S->values_dtype == FC_F64)
+            hipLaunchKernelGGL(k_check_csr<double>, dim3(g), dim3(256), 0, s, S->row_ptr, S->col_idx,
+                               (const double *)S->values, S->n, S->nnz, (int)(opt->diag == FC_DIAG_UNIT),
+                               1, flags);
+        else if (S->values_dtype == FC_F32)
+            hipLaunchKernelGGL(k_check_csr<float>, dim3(g), dim3(256), 0, s, S->row_ptr, S->col_idx,
+                               (const float *)S->values, S->n, S->nnz, (int)(opt->diag == FC_DIAG_UNIT),
+                               1, flags);
+        else
+            hipLaunchKernelGGL(k_check_csr<__half>, dim3(g), dim3(256), 0, s, S->row_ptr, S->col_idx,
+                               (const __half *)S->values, S->n, S->nnz, (int)(opt->diag == FC_DIAG_UNIT),
+                               1, flags);
+        int32_t hf = 0;
+        if (hipMemcpyAsync(&hf, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return cleanup(fail(FC_ERR_DEVICE, "validation readback"));
+        if (hf & 3)
+            return cleanup(fail(FC_ERR_NOT_SYMMETRIC, "CSR structure invalid (row_ptr or col_idx out of range)"));
+        if (hf & 4)
+            return cleanup(fail(FC_ERR_INVALID_ARG, "FC_DIAG_UNIT requires no stored diagonal entries"));
+        if (hf & 8)
+            return cleanup(fail(FC_ERR_NOT_SYMMETRIC, "validation needs sorted, duplicate-free rows"));
+        if (hf & 16)
+            return cleanup(fail(FC_ERR_NOT_SYMMETRIC, "S is not symmetric"));
+    }
+
+    const size_t esz = h->prec == FC_PREC_FP64 ? 8 : 4;
+    const size_t mat_bytes = (size_t)h->n * h->cp * esz;
+    for (int k = 0; k < 3; ++k) {
+        if (h->alloc(&h->X[k], mat_bytes) != hipSuccess || h->alloc(&h->Z[k], mat_bytes) != hipSuccess)
+            return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "iterate buffers"));
+        if (h->prec == FC_PREC_MIXED &&
+            h->alloc(&h->shadow[k], (size_t)h->n * h->cp * 2) != hipSuccess)
+            return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "bfloat16 shadow buffers"));
+    }
+    if (h->prec == FC_PREC_MIXED && S->values_dtype == FC_F32) {
+        if (h->alloc(&h->val_owned, (size_t)S->nnz * 2) != hipSuccess)
+            return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "half copy of S"));
+        hipLaunchKernelGGL((k_convert<float, __half>), dim3(grid_1d(S->nnz, 256, 8192)), dim3(256), 0, s,
+                           (const float *)S->values, (__half *)h->val_owned, S->nnz);
+        h->val = h->val_owned;
+        h->vdt = FC_F16;
+    }
+    if (h->alloc(&h->d_Xring, 3 * sizeof(void *)) != hipSuccess ||
+        h->alloc(&h->d_Zring, 3 * sizeof(void *)) != hipSuccess ||
+        h->alloc(&h->d_Sring, 3 * sizeof(void *)) != hipSuccess ||
+        h->alloc(&h->d_state, sizeof(DevState)) != hipSuccess ||
+        h->alloc(&h->d_GY64, sizeof(double) * h->cpm * h->cpm) != hipSuccess ||
+        h->alloc(&h->d_GYs, esz * h->cpm * h->cpm) != hipSuccess)
+        return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "solver state"));
+    if (hipMemcpyAsync(h->d_Xring, h->X, sizeof(h->X), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->d_Zring, h->Z, sizeof(h->Z), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(h->d_Sring, h->shadow, sizeof(h->shadow), hipMemcpyHostToDevice, s) != hipSuccess)
+        return cleanup(fail(FC_ERR_DEVICE, "pointer tables"));
+
+    // launch geometry: persistent grids sized to the device
+    const int cus = device_cus();
+    h->g_fused = grid_1d(h->n, 64, (int64_t)cus * 2);
+    h->g_gram = grid_1d(cdiv(h->n, 16), 4, (int64_t)cus * 2);
+    {
+        int rows_per_wg = 1;
+        with_cp(h->cp, [&](auto cpc) -> fc_status {
+            constexpr int CP = decltype(cpc)::value;
+            if (h->prec == FC_PREC_FP64)
+                rows_per_wg = SpmmCfg<double, CP>::ROWS_PER_WG;
+            else if (h->prec == FC_PREC_FP32)
+                rows_per_wg = SpmmCfg<float, CP>::ROWS_PER_WG;
+            else
+                rows_per_wg = SpmmCfg<__hip_bfloat16, CP>::ROWS_PER_WG;
+            return FC_OK;
+        });
+        h->g_spmm = grid_1d(h->n, rows_per_wg, (int64_t)cus * 32);
+    }
+    const int ne = fused_ne(h->cpm);
+    if (h->alloc(&h->d_part_fused, sizeof(double) * (size_t)h->g_fused * ne) != hipSuccess ||
+        h->alloc(&h->d_part_spmm, sizeof(double) * (size_t)h->g_spmm) != hipSuccess ||
+        h->alloc(&h->d_part_gram, sizeof(double) * (size_t)h->g_gram * 4 * h->cpm * h->cpm) != hipSuccess ||
+        h->alloc(&h->d_red_mats, sizeof(double) * ne) != hipSuccess ||
+        h->alloc(&h->d_red_trace, sizeof(double) * 2) != hipSuccess ||
+        h->alloc(&h->d_hist_f, sizeof(double) * h->hist_cap) != hipSuccess ||
+        h->alloc(&h->d_hist_tau, sizeof(double) * h->hist_cap) != hipSuccess ||
+        h->alloc(&h->d_hist_r, sizeof(double) * h->hist_cap) != hipSuccess ||
+        h->alloc(&h->d_hist_trials, sizeof(int32_t) * h->hist_cap) != hipSuccess)
+        return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "partial-sum buffers"));
+    if (hipMemsetAsync(h->d_red_mats, 0, sizeof(double) * ne, s) != hipSuccess ||
+        hipMemsetAsync(h->d_hist_trials, 0, sizeof(int32_t) * h->hist_cap, s) != hipSuccess)
+        return cleanup(fail(FC_ERR_DEVICE, "memset"));
+    if (opt->step_schedule) {
+        h->sched_len = opt->step_schedule_len;
+        if (h->alloc(&h->d_sched, sizeof(double) * h->sched_len) != hipSuccess)
+            return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "step schedule"));
+        if (hipMemcpyAsync(h->d_sched, opt->step_schedule, sizeof(double) * h->sched_len,
+                           hipMemcpyHostToDevice, s) != hipSuccess)
+            return cleanup(fail(FC_ERR_DEVICE, "step schedule copy"));
+        for (int k = 0; k < h->sched_len; ++k)
+            if (!(opt->step_schedule[k] > 0.0))
+                return cleanup(fail(FC_ERR_INVALID_ARG, "step schedule entries must be > 0"));
+    }
+
+    // Xbar_0 (the other two ring slots start as copies of it)
+    for (int k = 0; k < 3; ++k) {
+        const int g = grid_1d((int64_t)h->n * h->cp, 256, 8192);
+        if (h->prec == FC_PREC_FP64) {
+            if (!U0 || u0_dtype == FC_F64)
+                hipLaunchKernelGGL((k_pad_copy<double, double>), dim3(g), dim3(256), 0, s,
+                                   (const double *)U0, (int64_t)h->c, (double *)h->X[k], h->n, h->c, h->cp);
+            else
+                hipLaunchKernelGGL((k_pad_copy<float, double>), dim3(g), dim3(256), 0, s,
+                                   (const float *)U0, (int64_t)h->c, (double *)h->X[k], h->n, h->c, h->cp);
+        } else {
+            if (!U0 || u0_dtype == FC_F32)
+                hipLaunchKernelGGL((k_pad_copy<float, float>), dim3(g), dim3(256), 0, s,
+                                   (const float *)U0, (int64_t)h->c, (float *)h->X[k], h->n, h->c, h->cp);
+            else
+                hipLaunchKernelGGL((k_pad_copy<double, float>), dim3(g), dim3(256), 0, s,
+                                   (const double *)U0, (int64_t)h->c, (float *)h->X[k], h->n, h->c, h->cp);
+        }
+        if (hipMemsetAsync(h->Z[k], 0, mat_bytes, s) != hipSuccess)
+            return cleanup(fail(FC_ERR_DEVICE, "memset"));
+    }
+    if (hipGetLastError() != hipSuccess)
+        return cleanup(fail(FC_ERR_DEVICE, "start-point copy launch"));
+
+    // ||S_eff||_F^2 and the step bound of Theorem 3.1
+    double s2 = 0.0;
+    fc_csr Sv = *S;
+    Sv.values = h->val;
+    Sv.values_dtype = h->vdt;
+    st = sum_squares(&Sv, s, &s2);
+    if (st != FC_OK)
+        return cleanup(st);
+    if (h->diag == FC_DIAG_UNIT)
+        s2 += (double)h->n;
+    const bool need_L = (!h->backtrack && !(opt->step > 0.0) && !opt->step_schedule) ||
+                        (h->backtrack && !(opt->L0 > 0.0));
+    if (need_L) {
+        int32_t its = 0;
+        st = power_norm(&Sv, (int)(h->diag == FC_DIAG_UNIT), 1000, 1e-12, s, &h->spec_norm, &its);
+        if (st != FC_OK)
+            return cleanup(st);
+        h->L_thm = 4.0 * h->spec_norm + 12.0 * (double)h->n;
+    }
+
+    DevState &d = h->h;
+    std::memset(&d, 0, sizeof(d));
+    d.role[ROLE_C] = 0;
+    d.role[ROLE_P] = 1;
+    d.role[ROLE_N] = 2;
+    d.active = 1;
+    d.target = 0;
+    d.max_iter = INT_MAX;
+    d.accelerate = h->accelerate;
+    d.backtrack = h->backtrack;
+    d.c = h->c;
+    d.hist_cap = h->hist_cap;
+    d.sched_len = h->sched_len;
+    d.t = 1.0;
+    d.beta = 0.0;
+    d.beta_next = 0.0;
+    d.s2 = s2;
+    d.tol_loss = opt->tol_loss;
+    d.tol_pgrad = opt->tol_pgrad;
+    d.eta = opt->eta > 1.0 ? opt->eta : 2.0;
+    if (h->backtrack) {
+        d.L = opt->L0 > 0.0 ? opt->L0 : h->L_thm / 100.0;
+        d.tau = 1.0 / d.L;
+    } else {
+        d.tau0 = opt->step_schedule ? opt->step_schedule[0] : (opt->step > 0.0 ? opt->step : 1.0 / h->L_thm);
+        d.tau = d.tau0;
+        d.L = 1.0 / d.tau;
+    }
+    st = write_state(h);
+    if (st != FC_OK)
+        return cleanup(st);
+    st = launch_init(h);
+    if (st != FC_OK)
+        return cleanup(st);
+    st = read_state(h);
+    if (st != FC_OK)
+        return cleanup(st);
+    if (h->h.error != ERR_NONE)
+        return cleanup(status_of(h));
+    *out = h;
+    return FC_OK;
+}
+
+fc_status fc_step(fc_solver *h, int32_t iters, fc_info *info) {
+    g_last_error.clear();
+    if (!h)
+        return fail(FC_ERR_INVALID_ARG, "solver is NULL");
+    if (iters < 0)
+        return fail(FC_ERR_INVALID_ARG, "iters < 0");
+    fc_status st = FC_OK;
+    if (iters > 0) {
+        const int64_t target = (int64_t)h->h.iter + iters;
+        st = run_until(h, (int32_t)(target > INT_MAX ? INT_MAX : target), INT_MAX);
+    }
+    fill_info(h, info);
+    return st;
+}
+
+fc_status fc_solve(fc_solver *h, fc_info *info) {
+    g_last_error.clear();
+    if (!h)
+        return fail(FC_ERR_INVALID_ARG, "solver is NULL");
+    fc_status st = FC_OK;
+    if (h->h.iter < h->max_iter &&
+        !(h->h.stop_reason == STOP_LOSS || h->h.stop_reason == STOP_PGRAD))
+        st = run_until(h, h->max_iter, h->max_iter);
+    else if (h->h.iter >= h->max_iter && h->h.stop_reason == STOP_NONE)
+        h->h.stop_reason = STOP_MAXITER;
+    fill_info(h, info);
+    return st;
+}
+
+fc_status fc_get_u(const fc_solver *h, void *U_out, fc_dtype dtype) {
+    g_last_error.clear();
+    if (!h || !U_out)
+        return fail(FC_ERR_INVALID_ARG, "NULL argument");
+    if (dtype != FC_F64 && dtype != FC_F32)
+        return fail(FC_ERR_INVALID_ARG, "U_out must be FC_F64 or FC_F32");
+    const void *src = h->X[h->h.role[ROLE_C]];
+    const int g = grid_1d(h->n * h->c, 256, 8192);
+    hipStream_t s = h->stream;
+    if (h->prec == FC_PREC_FP64) {
+        if (dtype == FC_F64)
+            hipLaunchKernelGGL((k_unpad_copy<double, double>), dim3(g), dim3(256), 0, s,
+                               (const double *)src, h->cp, (double *)U_out, h->n, h->c);
+        else
+            hipLaunchKernelGGL((k_unpad_copy<double, float>), dim3(g), dim3(256), 0, s,
+                               (const double *)src, h->cp, (float *)U_out, h->n, h->c);
+    } else {
+        if (dtype == FC_F64)
+            hipLaunchKernelGGL((k_unpad_copy<float, double>), dim3(g), dim3(256), 0, s,
+                               (const float *)src, h->cp, (double *)U_out, h->n, h->c);
+        else
+            hipLaunchKernelGGL((k_unpad_copy<float, float>), dim3(g), dim3(256), 0, s,
+                               (const float *)src, h->cp, (float *)U_out, h->n, h->c);
+    }
+    HIPCHK(hipGetLastError());
+    return FC_OK;
+}
+
+fc_status fc_get_history(const fc_solver *h, int32_t cap, double *f_log, double *step_log,
+                         int32_t *trials_log, double *r_log, int32_t *count) {
+    g_last_error.clear();
+    if (!h || cap < 0)
+        return fail(FC_ERR_INVALID_ARG, "bad argument");
+    int32_t k = h->h.iter + 1;
+    if (k > h->hist_cap)
+        k = h->hist_cap;
+    if (k > cap)
+        k = cap;
+    hipStream_t s = h->stream;
+    if (f_log && k > 0)
+        HIPCHK(hipMemcpyAsync(f_log, h->d_hist_f, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    if (step_log && k > 0)
+        HIPCHK(hipMemcpyAsync(step_log, h->d_hist_tau, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    if (trials_log && k > 0)
+        HIPCHK(hipMemcpyAsync(trials_log, h->d_hist_trials, sizeof(int32_t) * k, hipMemcpyDeviceToHost, s));
+    if (r_log && k > 0)
+        HIPCHK(hipMemcpyAsync(r_log, h->d_hist_r, sizeof(double) * k, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (step_log && k > 0)
+        step_log[0] = 0.0;
+    if (r_log && k > 0)
+        r_log[0] = 0.0;
+    if (trials_log && k > 0)
+        trials_log[0] = 0;
+    if (count)
+        *count = k;
+    return FC_OK;
+}
+
+fc_status fc_get_state(const fc_solver *h, void *buf, size_t *bytes) {
+    (void)h;
+    (void)buf;
+    (void)bytes;
+    return fail(FC_ERR_UNSUPPORTED, "checkpointing is not implemented yet");
+}
+
+fc_status fc_set_state(fc_solver *h, const void *buf, size_t bytes) {
+    (void)h;
+    (void)buf;
+    (void)bytes;
+    return fail(FC_ERR_UNSUPPORTED, "checkpointing is not implemented yet");
+}
+
+void fc_destroy(fc_solver *h) {
+    if (!h)
+        return;
+    if (h->stream)
+        (void)hipStreamSynchronize(h->stream);
+    else
+        (void)hipDeviceSynchronize();
+    delete h;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// stateless entry points
+// ---------------------------------------------------------------------------
+namespace {
+
+template <typename T, typename VS, int CP>
+fc_status spmm_and_gram_t(const fc_csr *S, fc_diag diag, const T *Upad, T *Zpad, bool want_gram,
+                          hipStream_t s, double *trace_out, double *G_out) {
+    constexpr int CPM = CP < 16 ? 16 : CP;
+    using Cfg = SpmmCfg<T, CP>;
+    const int64_t n = S->n;
+    const int cus = device_cus();
+    const int g_spmm = grid_1d(n, Cfg::ROWS_PER_WG, (int64_t)cus * 32);
+    DevBuf ring, part, red;
+    HIPCHK(dev_alloc(ring, 2 * sizeof(void *), s));
+    const void *ptrs[2] = {Upad, Zpad};
+    HIPCHK(hipMemcpyAsync(ring.p, ptrs, sizeof(ptrs), hipMemcpyHostToDevice, s));
+    const T *const *Ur = (const T *const *)ring.p;
+    T *const *Zr = (T *const *)((void **)ring.p + 1);
+    HIPCHK(dev_alloc(part, sizeof(double) * g_spmm, s));
+    HIPCHK(dev_alloc(red, sizeof(double) * (1 + CPM * CPM), s));
+    hipLaunchKernelGGL((k_spmm<T, T, T, VS, CP>), dim3(g_spmm), dim3(256), 0, s, S->row_ptr,
+                       S->col_idx, (const VS *)S->values, Ur, Ur, Zr, n, (int)(diag == FC_DIAG_UNIT),
+                       (double *)part.p, (const DevState *)nullptr, 0);
+    launch_reduce((const double *)part.p, g_spmm, 1, 1, (double *)red.p, s);
+    DevBuf gpart;
+    if (want_gram) {
+        const int g_gram = grid_1d(cdiv(n, 16), 4, (int64_t)cus * 2);
+        HIPCHK(dev_alloc(gpart, sizeof(double) * (size_t)g_gram * 4 * CPM * CPM, s));
+        hipLaunchKernelGGL((k_gram<T, CP>), dim3(g_gram), dim3(256), 0, s, Upad, n,
+                           (double *)gpart.p, (int64_t)(CPM * CPM));
+        launch_reduce((const double *)gpart.p, (int64_t)g_gram * 4, CPM * CPM, CPM * CPM,
+                      (double *)red.p + 1, s);
+    }
+    HIPCHK(hipGetLastError());
+    std::vector<double> hbuf(1 + CPM * CPM);
+    HIPCHK(hipMemcpyAsync(hbuf.data(), red.p, sizeof(double) * (want_gram ? 1 + CPM * CPM : 1),
+                          hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (trace_out)
+        *trace_out = hbuf[0];
+    if (G_out && want_gram)
+        std::memcpy(G_out, hbuf.data() + 1, sizeof(double) * CPM * CPM);
+    return FC_OK;
+}
+
+// Copy a user matrix (n x c, ld = c) into a padded device buffer of type T.
+template <typename T>
+fc_status pad_user(const void *U, fc_dtype dt, int64_t n, int c, int cp, T *dst, hipStream_t s) {
+    const int g = grid_1d(n * cp, 256, 8192);
+    if (dt == FC_F64)
+        hipLaunchKernelGGL((k_pad_copy<double, T>), dim3(g), dim3(256), 0, s, (const double *)U,
+                           (int64_t)c, dst, n, c, cp);
+    else
+        hipLaunchKernelGGL((k_pad_copy<float, T>), dim3(g), dim3(256), 0, s, (const float *)U,
+                           (int64_t)c, dst, n, c, cp);
+    HIPCHK(hipGetLastError());
+    return FC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fc_status fc_spmm(const fc_csr *S, fc_diag diag, const void *U, void *Z, fc_dtype dtype, int32_t c,
+                  void *stream) {
+    g_last_error.clear();
+    fc_status st = check_csr_args(S);
+    if (st != FC_OK)
+        return st;
+    if (!U || !Z)
+        return fail(FC_ERR_INVALID_ARG, "U or Z is NULL");
+    if (c < 1 || c > 64)
+        return fail(FC_ERR_INVALID_ARG, "c must be in [1, 64]");
+    if (dtype != FC_F64 && dtype != FC_F32)
+        return fail(FC_ERR_INVALID_ARG, "dtype must be FC_F64 or FC_F32");
+    if ((dtype == FC_F64) != (S->values_dtype == FC_F64))
+        return fail(FC_ERR_INVALID_ARG, "S values and U must both be FC_F64, or FC_F32/FC_F16 with FC_F32 U");
+    hipStream_t s = (hipStream_t)stream;
+    const int cp = cp_of(c);
+    const size_t esz = dtype == FC_F64 ? 8 : 4;
+    DevBuf up, zp;
+    HIPCHK(dev_alloc(up, esz * S->n * cp, s));
+    HIPCHK(dev_alloc(zp, esz * S->n * cp, s));
+    return with_cp(cp, [&](auto cpc) -> fc_status {
+        constexpr int CP = decltype(cpc)::value;
+        fc_status r;
+        const int g = grid_1d(S->n * c, 256, 8192);
+        if (dtype == FC_F64) {
+            r = pad_user<double>(U, dtype, S->n, c, CP, (double *)up.p, s);
+            if (r != FC_OK)
+                return r;
+            r = spmm_and_gram_t<double, double, CP>(S, diag, (const double *)up.p, (double *)zp.p,
+                                                    false, s, nullptr, nullptr);
+            if (r != FC_OK)
+                return r;
+            hipLaunchKernelGGL((k_unpad_copy<double, double>), dim3(g), dim3(256), 0, s,
+                               (const double *)zp.p, CP, (double *)Z, S->n, c);
+        } else {
+            r = pad_user<float>(U, dtype, S->n, c, CP, (float *)up.p, s);
+            if (r != FC_OK)
+                return r;
+            if (S->values_dtype == FC_F16)
+                r = spmm_and_gram_t<float, __half, CP>(S, diag, (const float *)up.p, (float *)zp.p,
+                                                       false, s, nullptr, nullptr);
+            else
+                r = spmm_and_gram_t<float, float, CP>(S, diag, (const float *)up.p, (float *)zp.p,
+                                                      false, s, nullptr, nullptr);
+            if (r != FC_OK)
+                return r;
+            hipLaunchKernelGGL((k_unpad_copy<float, float>), dim3(g), dim3(256), 0, s,
+                               (const float *)zp.p, CP, (float *)Z, S->n, c);
+        }
+        HIPCHK(hipGetLastError());
+        return FC_OK;
+    });
+}
+
+fc_status fc_objective(const fc_csr *S, fc_diag diag, const void *U, fc_dtype u_dtype, int32_t c,
+                       void *stream, double *f_out) {
+    g_last_error.clear();
+    fc_status st = check_csr_args(S);
+    if (st != FC_OK)
+        return st;
+    if (!U || !f_out)
+        return fail(FC_ERR_INVALID_ARG, "U or f_out is NULL");
+    if (c < 1 || c > 64)
+        return fail(FC_ERR_INVALID_ARG, "c must be in [1, 64]");
+    if (u_dtype != FC_F64 && u_dtype != FC_F32)
+        return fail(FC_ERR_INVALID_ARG, "u_dtype must be FC_F64 or FC_F32");
+    if ((u_dtype == FC_F64) != (S->values_dtype == FC_F64))
+        return fail(FC_ERR_INVALID_ARG, "S values and U must both be FC_F64, or FC_F32/FC_F16 with FC_F32 U");
+    hipStream_t s = (hipStream_t)stream;
+    const int cp = cp_of(c);
+    const int cpm = cpm_of(cp);
+    double s2 = 0.0;
+    st = sum_squares(S, s, &s2);
+    if (st != FC_OK)
+        return st;
+    if (diag == FC_DIAG_UNIT)
+        s2 += (double)S->n;
+    const size_t esz = u_dtype == FC_F64 ? 8 : 4;
+    DevBuf up, zp;
+    HIPCHK(dev_alloc(up, esz * S->n * cp, s));
+    HIPCHK(dev_alloc(zp, esz * S->n * cp, s));
+    std::vector<double> G(cpm * cpm);
+    double tr = 0.0;
+    st = with_cp(cp, [&](auto cpc) -> fc_status {
+        constexpr int CP = decltype(cpc)::value;
+        fc_status r;
+        if (u_dtype == FC_F64) {
+            r = pad_user<double>(U, u_dtype, S->n, c, CP, (double *)up.p, s);
+            if (r != FC_OK)
+                return r;
+            return spmm_and_gram_t<double, double, CP>(S, diag, (const double *)up.p, (double *)zp.p,
+                                                       true, s, &tr, G.data());
+        }
+        r = pad_user<float>(U, u_dtype, S->n, c, CP, (float *)up.p, s);
+        if (r != FC_OK)
+            return r;
+        if (S->values_dtype == FC_F16)
+            return spmm_and_gram_t<float, __half, CP>(S, diag, (const float *)up.p, (float *)zp.p, true,
+                                                      s, &tr, G.data());
+        return spmm_and_gram_t<float, float, CP>(S, diag, (const float *)up.p, (float *)zp.p, true, s,
+                                                 &tr, G.data());
+    });
+    if (st != FC_OK)
+        return st;
+    double gsq = 0.0;
+    for (double g : G)
+        gsq += g * g;
+    *f_out = s2 + gsq - 2.0 * tr;
+    return FC_OK;
+}
+
+fc_status fc_gram(const void *U, fc_dtype dtype, int64_t n, int32_t c, void *stream, double *G_out) {
+    g_last_error.clear();
+    if (!U || !G_out)
+        return fail(FC_ERR_INVALID_ARG, "U or G_out is NULL");
+    if (n < 1 || c < 1 || c > 64)
+        return fail(FC_ERR_INVALID_ARG, "need n >= 1 and c in [1, 64]");
+    if (dtype != FC_F64 && dtype != FC_F32)
+        return fail(FC_ERR_INVALID_ARG, "dtype must be FC_F64 or FC_F32");
+    hipStream_t s = (hipStream_t)stream;
+    const int cp = cp_of(c);
+    const int cpm = cpm_of(cp);
+    const size_t esz = dtype == FC_F64 ? 8 : 4;
+    DevBuf up, gpart, red;
+    HIPCHK(dev_alloc(up, esz * n * cp, s));
+    const int cus = device_cus();
+    const int g_gram = grid_1d(cdiv(n, 16), 4, (int64_t)cus * 2);
+    HIPCHK(dev_alloc(gpart, sizeof(double) * (size_t)g_gram * 4 * cpm * cpm, s));
+    HIPCHK(dev_alloc(red, sizeof(double) * cpm * cpm, s));
+    fc_status st = with_cp(cp, [&](auto cpc) -> fc_status {
+        constexpr int CP = decltype(cpc)::value;
+        fc_status r;
+        if (dtype == FC_F64) {
+            r = pad_user<double>(U, dtype, n, c, CP, (double *)up.p, s);
+            if (r != FC_OK)
+                return r;
+            hipLaunchKernelGGL((k_gram<double, CP>), dim3(g_gram), dim3(256), 0, s,
+                               (const double *)up.p, n, (double *)gpart.p, (int64_t)(cpm * cpm));
+        } else {
+            r = pad_user<float>(U, dtype, n, c, CP, (float *)up.p, s);
+            if (r != FC_OK)
+                return r;
+            hipLaunchKernelGGL((k_gram<float, CP>), dim3(g_gram), dim3(256), 0, s,
+                               (const float *)up.p, n, (double *)gpart.p, (int64_t)(cpm * cpm));
+        }
+        HIPCHK(hipGetLastError());
+        return FC_OK;
+    });
+    if (st != FC_OK)
+        return st;
+    launch_reduce((const double *)gpart.p, (int64_t)g_gram * 4, cpm * cpm, cpm * cpm, (double *)red.p, s);
+    std::vector<double> G(cpm * cpm);
+    HIPCHK(hipMemcpyAsync(G.data(), red.p, sizeof(double) * cpm * cpm, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < c; ++i)
+        for (int j = 0; j < c; ++j)
+            G_out[i * c + j] = G[i * cpm + j];
+    return FC_OK;
+}
+
+fc_status fc_project(const void *V, void *out, fc_dtype dtype, int64_t rows, int32_t c, int64_t ld,
+                     void *stream) {
+    g_last_error.clear();
+    if (!V || !out)
+        return fail(FC_ERR_INVALID_ARG, "V or out is NULL");
+    if (rows < 0 || c < 1 || c > 64 || ld < c)
+        return fail(FC_ERR_INVALID_ARG, "need rows >= 0, c in [1, 64], ld >= c");
+    if (dtype != FC_F64 && dtype != FC_F32)
+        return fail(FC_ERR_INVALID_ARG, "dtype must be FC_F64 or FC_F32");
+    if (rows == 0)
+        return FC_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const int cpm = cpm_of(cp_of(c));
+    const int cus = device_cus();
+    const int g = grid_1d(cdiv(rows, 16), 4, (int64_t)cus * 8);
+#define PROJ(T, CPMV)                                                                             \
+    hipLaunchKernelGGL((k_project<T, CPMV>), dim3(g), dim3(256), 0, s, (const T *)V, (T *)out, rows, \
+                       c, ld)
+    if (dtype == FC_F64) {
+        if (cpm == 16) PROJ(double, 16);
+        else if (cpm == 32) PROJ(double, 32);
+        else PROJ(double, 64);
+    } else {
+        if (cpm == 16) PROJ(float, 16);
+        else if (cpm == 32) PROJ(float, 32);
+        else PROJ(float, 64);
+    }
+#undef PROJ
+    HIPCHK(hipGetLastError());
+    return FC_OK;
+}
+
+fc_status fc_spectral_norm(const fc_csr *S, fc_diag diag, int32_t max_iter, double rtol, void *stream,
+                           double *norm_out, int32_t *iters_out) {
+    g_last_error.clear();
+    fc_status st = check_csr_args(S);
+    if (st != FC_OK)
+        return st;
+    if (!norm_out)
+        return fail(FC_ERR_INVALID_ARG, "norm_out is NULL");
+    return power_norm(S, (int)(diag == FC_DIAG_UNIT), max_iter, rtol, (hipStream_t)stream, norm_out,
+                      iters_out);
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+"""Boundary checks that need no GPU: the built library exports every entry
+point include/fc.h declares, the ctypes layouts match the C structs, the
+argument checks fail before any device work, and the product path does not
+reach the oracle."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fc.h")
+
+
+@pytest.fixture(scope="module")
+def N():
+    from paper_2506_04045_amd import _native
+    if not os.path.exists(_native.LIB_PATH):
+        from paper_2506_04045_amd import build
+        build.build()
+    _native.load()
+    return _native
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fc_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("fc_create", "fc_step", "fc_solve", "fc_objective", "fc_project",
+                     "fc_destroy", "fc_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(N):
+    lib = ctypes.CDLL(N.LIB_PATH)
+    missing = [name for name in declared_functions() if not hasattr(lib, name)]
+    assert not missing, missing
+    assert sorted(N.EXPORTED) == declared_functions()
+
+
+def test_struct_layouts(N):
+    o = N.default_options()
+    assert o.struct_size == ctypes.sizeof(N.Options) == 96
+    assert ctypes.sizeof(N.CSR) == 48 and ctypes.sizeof(N.Info) == 72
+    assert o.eta == 2.0 and o.max_iter == 100 and o.check_every == 16
+    assert o.precision == N.FC_PREC_FP32 and o.diag == N.FC_DIAG_UNIT and o.accelerate == 1
+    assert o.tol_loss != o.tol_loss  # NaN disables the loss stop by default
+
+
+def test_argument_errors_before_device_work(N):
+    lib = N.load()
+    h = ctypes.c_void_p()
+    opt = N.default_options()
+    assert lib.fc_create(None, ctypes.byref(opt), None, N.FC_F32, None, ctypes.byref(h)) == \
+        N.FC_ERR_INVALID_ARG
+    assert b"NULL" in lib.fc_last_error()
+    csr = N.CSR(0, 0, None, None, None, N.FC_F32)
+    assert lib.fc_create(ctypes.byref(csr), ctypes.byref(opt), None, N.FC_F32, None,
+                         ctypes.byref(h)) == N.FC_ERR_INVALID_ARG
+    csr = N.CSR(10, 0, 1, None, None, N.FC_F32)   # fake pointer, never dereferenced
+    opt.c = 0
+    assert lib.fc_create(ctypes.byref(csr), ctypes.byref(opt), None, N.FC_F32, None,
+                         ctypes.byref(h)) == N.FC_ERR_INVALID_ARG
+    assert b"c must be" in lib.fc_last_error()
+    opt.c = 65
+    assert lib.fc_create(ctypes.byref(csr), ctypes.byref(opt), None, N.FC_F32, None,
+                         ctypes.byref(h)) == N.FC_ERR_INVALID_ARG
+    opt.c = 8
+    opt.precision = N.FC_PREC_FP64       # FP64 needs FC_F64 values
+    assert lib.fc_create(ctypes.byref(csr), ctypes.byref(opt), None, N.FC_F32, None,
+                         ctypes.byref(h)) == N.FC_ERR_INVALID_ARG
+    bad = N.Options()
+    assert lib.fc_create(ctypes.byref(csr), ctypes.byref(bad), None, N.FC_F32, None,
+                         ctypes.byref(h)) == N.FC_ERR_INVALID_ARG
+    assert b"struct_size" in lib.fc_last_error()
+    assert lib.fc_project(None, None, N.FC_F32, 4, 3, 3, None) == N.FC_ERR_INVALID_ARG
+    assert lib.fc_project(1, 1, N.FC_F32, 4, 3, 2, None) == N.FC_ERR_INVALID_ARG  # ld < c
+    assert lib.fc_project(1, 1, N.FC_F16, 4, 3, 3, None) == N.FC_ERR_INVALID_ARG
+    assert lib.fc_spmm(ctypes.byref(csr), N.FC_DIAG_UNIT, 1, 1, N.FC_F32, 0, None) == \
+        N.FC_ERR_INVALID_ARG
+    f = ctypes.c_double()
+    assert lib.fc_objective(ctypes.byref(csr), N.FC_DIAG_UNIT, 1, N.FC_F64, 4, None,
+                            ctypes.byref(f)) == N.FC_ERR_INVALID_ARG
+    assert lib.fc_gram(None, N.FC_F32, 4, 3, None, None) == N.FC_ERR_INVALID_ARG
+    assert lib.fc_step(None, 1, None) == N.FC_ERR_INVALID_ARG
+    assert lib.fc_solve(None, None) == N.FC_ERR_INVALID_ARG
+    lib.fc_destroy(None)
+
+
+def test_product_code_does_not_use_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2506_04045_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for fn in files:
+            if fn.endswith((".py", ".hip", ".hpp", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, fn)).read()
+                assert "import oracle" not in text and "fcref" not in text, fn
+                assert "from oracle" not in text, fn
+    # and the oracle does not use the product
+    for fn in os.listdir(os.path.join(ROOT, "oracle")):
+        if fn.endswith((".py", ".c")):
+            text = open(os.path.join(ROOT, "oracle", fn)).read()
+            assert "paper_2506_04045_amd" not in text and "fc_kernels" not in text, fn
+
+
+def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
+    from paper_2506_04045_amd import _native
+    monkeypatch.setattr(_native, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(_native, "_lib", None)
+    with pytest.raises(RuntimeError, match="no CPU fallback"):
+        _native.load()

@@ -1,0 +1,257 @@
+"""Solver-level parity of the HIP path against the FP64 oracle (Alg. 2-4),
+called through the C ABI.
+
+Tolerances (stated in the fuzzy-clustering workload's parity bar):
+* FP64 on the GPU follows the oracle to rounding: per-iteration losses within
+  1e-9 relative, iterates within 1e-9.
+* FP32 on the GPU against the FP64 oracle: final loss within 1e-4 relative,
+  the loss decrease f(U0) - f(U_K) within 1e-3 relative, iterates within
+  1e-4, rows summing to 1 within 1e-6.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from tests import pins
+from tests.gpu_util import csr_to_dev, dev
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fc():
+    import paper_2506_04045_amd as fc
+    fc.library_path()
+    return fc
+
+
+@pytest.fixture(scope="module")
+def small():
+    """The n = 2,000, c = 8 workload (Dirichlet(0.3) planted rows, ER
+    degree 20, sigma 0.02) with a Dirichlet(1) start."""
+    wl = W.config_small_fp64(seed=0)
+    rp, ci, v, U0 = wl.numpy()
+    spec, _ = oracle.spectral_norm(rp, ci, v, True)
+    return dict(rp=rp, ci=ci, v=v, U0=U0, n=wl.n, c=wl.c,
+                tau=1.0 / oracle.lipschitz_bound(spec, wl.n))
+
+
+def _solve_gpu(fc, rp, ci, v, U0, c, prec, iters, **kw):
+    vd = torch.float64 if prec == "fp64" else torch.float32
+    ud = torch.float64 if prec == "fp64" else torch.float32
+    S = csr_to_dev(rp, ci, v, vd)
+    with fc.Solver(*S, c, dev(U0, ud), precision=prec, **kw) as s:
+        info = s.step(iters)
+        U = s.get_u(torch.float64).cpu().numpy()
+        hist = s.history()
+    return info, U, hist
+
+
+def test_small_fp64_trajectory(fc, small):
+    d = small
+    ref = oracle.solve(d["rp"], d["ci"], d["v"], True, d["U0"], accelerate=True, max_iter=200,
+                       step=d["tau"])
+    info, U, hist = _solve_gpu(fc, d["rp"], d["ci"], d["v"], d["U0"], d["c"], "fp64", 200)
+    assert info.iter == 200
+    # the device computed tau = 1/L_thm by its own power iteration
+    assert hist["tau"][1] == pytest.approx(d["tau"], rel=1e-10)
+    assert np.abs(hist["f"] - ref.f).max() <= 1e-9 * abs(ref.f[0])
+    assert np.abs(U - ref.X).max() <= 1e-9
+
+
+def test_small_fp32_against_fp64_oracle(fc, small):
+    d = small
+    U0 = d["U0"].astype(np.float32).astype(np.float64)
+    v = d["v"].astype(np.float32).astype(np.float64)
+    ref = oracle.solve(d["rp"], d["ci"], v, True, U0, accelerate=True, max_iter=200,
+                       step=d["tau"])
+    info, U, hist = _solve_gpu(fc, d["rp"], d["ci"], v, U0, d["c"], "fp32", 200, step=d["tau"])
+    f_rel = abs(info.f - ref.f[-1]) / abs(ref.f[-1])
+    df_ref = ref.f[0] - ref.f[-1]
+    df_rel = abs((hist["f"][0] - info.f) - df_ref) / abs(df_ref)
+    print(f"fp32 small: f_rel={f_rel:.2e} df_rel={df_rel:.2e} "
+          f"max|dU|={np.abs(U - ref.X).max():.2e}")
+    assert f_rel <= 1e-4
+    assert df_rel <= 1e-3
+    assert np.abs(U - ref.X).max() <= 1e-4
+    assert np.abs(U.sum(1) - 1).max() <= 1e-6
+    assert (U >= 0).all()
+
+
+def test_uniform_start_is_a_fixed_point(fc, small):
+    d = small
+    U0 = np.full((d["n"], d["c"]), 1.0 / d["c"])
+    info, U, hist = _solve_gpu(fc, d["rp"], d["ci"], d["v"], U0, d["c"], "fp64", 200)
+    assert np.abs(U - U0).max() <= 1e-12
+    assert np.ptp(hist["f"]) <= 1e-12 * abs(hist["f"][0])
+    # U0 = NULL means the same constant start
+    S = csr_to_dev(d["rp"], d["ci"], d["v"], torch.float64)
+    with fc.Solver(*S, d["c"], None, precision="fp64") as s:
+        s.step(5)
+        assert np.abs(s.get_u(torch.float64).cpu().numpy() - U0).max() <= 1e-12
+
+
+@pytest.mark.parametrize("diag", ["stored", "unit"])
+@pytest.mark.parametrize("accelerate", [False, True])
+@pytest.mark.parametrize("c", [1, 3, 17, 33, 64])
+def test_fp64_parity_shapes(fc, diag, accelerate, c):
+    n = 1000 + 41
+    wl = W.er_planted(n, c, 8.0, 0.05, c, val_dtype=torch.float64, u_dtype=torch.float64)
+    rp, ci, v, U0 = wl.numpy()
+    if diag == "stored":   # store a diagonal to exercise that mode
+        A = pins.dense_similarity(rp, ci, v, False, n) + np.diag(np.linspace(0.2, 0.9, n))
+        rp, ci, v = pins.csr_from_dense(A)
+    tau = 2e-4
+    ref = oracle.solve(rp, ci, v, diag == "unit", U0, accelerate=accelerate, max_iter=25, step=tau)
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, c, "fp64", 25, step=tau, diag=diag,
+                               accelerate=accelerate)
+    assert np.abs(hist["f"] - ref.f).max() <= 1e-9 * abs(ref.f[0])
+    assert np.abs(U - ref.X).max() <= 1e-9
+
+
+def test_backtracking_fp64_follows_the_oracle(fc):
+    wl = W.er_planted(20000, 16, 20.0, 0.05, 4, val_dtype=torch.float64, u_dtype=torch.float64)
+    rp, ci, v, U0 = wl.numpy()
+    ref = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=40, backtrack=True, L0=10.0)
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, 16, "fp64", 40, backtrack=True, L0=10.0)
+    assert (hist["trials"][1:] == ref.trials[1:]).all()
+    assert np.array_equal(hist["tau"][1:], ref.tau[1:])
+    assert np.abs(hist["f"] - ref.f).max() <= 1e-9 * abs(ref.f[0])
+    assert np.abs(U - ref.X).max() <= 1e-8
+    assert info.trials == int(ref.trials[1:].sum())
+
+
+def test_fp32_replays_the_oracle_step_sequence(fc):
+    wl = W.er_planted(20000, 32, 30.0, 0.05, 5)
+    rp, ci, v, U0 = wl.numpy()
+    ref = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=60, backtrack=True, L0=10.0)
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, 32, "fp32", 60, step_schedule=ref.tau[1:])
+    f_rel = abs(info.f - ref.f[-1]) / abs(ref.f[-1])
+    print(f"replay fp32: f_rel={f_rel:.2e} max|dU|={np.abs(U - ref.X).max():.2e}")
+    assert f_rel <= 1e-4
+    assert np.abs(U - ref.X).max() <= 1e-4
+    assert np.abs(U.sum(1) - 1).max() <= 1e-6
+    # free-running FP32 backtracking takes (nearly) the same decisions
+    info2, U2, hist2 = _solve_gpu(fc, rp, ci, v, U0, 32, "fp32", 60, backtrack=True, L0=10.0)
+    agree = np.mean(hist2["tau"][1:] == ref.tau[1:])
+    print(f"free-running fp32 backtracking: step agreement {agree:.3f}")
+    assert agree >= 0.9
+
+
+def test_gpa_loss_stop_example41(fc):
+    ex = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "example41.json")))
+    S = np.array(ex["S"], dtype=float)
+    rp, ci, v = pins.csr_from_dense(S)
+    X0 = np.zeros((7, 2))
+    X0[:, 0] = 1.0
+    ref = oracle.solve(rp, ci, v, False, X0, accelerate=False, max_iter=5000, step=0.1,
+                       tol_loss=0.0)
+    Sd = csr_to_dev(rp, ci, v, torch.float64)
+    with fc.Solver(*Sd, 2, dev(X0, torch.float64), precision="fp64", diag="stored",
+                   accelerate=False, step=0.1, tol_loss=0.0, max_iter=5000) as s:
+        info = s.solve()
+        U = s.get_u(torch.float64).cpu().numpy()
+    assert info.stop_reason == 2  # FC_STOP_LOSS
+    assert info.iter == ref.iters
+    assert round(info.f, 2) == ex["scenario2"]["loss"]
+    assert np.abs(U - ref.X).max() <= 1e-12
+    # scenario 3: the uniform start stops after one iteration, unchanged
+    X3 = np.full((7, 2), 0.5)
+    with fc.Solver(*Sd, 2, dev(X3, torch.float64), precision="fp64", diag="stored",
+                   accelerate=False, step=0.1, tol_loss=0.0, max_iter=50) as s:
+        info = s.solve()
+        assert info.iter == 1 and info.f == pytest.approx(12.25, abs=1e-12)
+        assert np.abs(s.get_u(torch.float64).cpu().numpy() - 0.5).max() == 0.0
+
+
+def test_pgrad_stop_matches_the_oracle(fc):
+    wl = W.er_planted(3000, 8, 10.0, 0.05, 6, val_dtype=torch.float64, u_dtype=torch.float64)
+    rp, ci, v, U0 = wl.numpy()
+    ref = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=300, backtrack=True,
+                       L0=1.0, tol_pgrad=1e-2)
+    Sd = csr_to_dev(rp, ci, v, torch.float64)
+    with fc.Solver(*Sd, 8, dev(U0, torch.float64), precision="fp64", backtrack=True, L0=1.0,
+                   tol_pgrad=1e-2, max_iter=300, check_every=7) as s:
+        info = s.solve()
+        hist = s.history()
+    assert ref.stop_reason == oracle.STOP_PGRAD and info.stop_reason == 3
+    assert info.iter == ref.iters
+    assert np.allclose(hist["r"][1:], ref.r[1:], rtol=1e-9)
+
+
+def test_step_calls_compose_and_are_deterministic(fc):
+    wl = W.er_planted(5000, 32, 15.0, 0.05, 7)
+    S = wl.to("cuda")
+    outs = []
+    for split in ([7], [3, 4], [1, 1, 5]):
+        with fc.Solver(S.row_ptr, S.col_idx, S.val, 32, S.U0, step=1e-3) as s:
+            for k in split:
+                s.step(k)
+            outs.append((s.get_u().cpu().numpy(), s.info().f))
+    for U, f in outs[1:]:
+        assert np.array_equal(U, outs[0][0]) and f == outs[0][1]
+
+
+def test_solve_budget_and_info(fc):
+    wl = W.er_planted(3000, 8, 10.0, 0.05, 8)
+    S = wl.to("cuda")
+    with fc.Solver(S.row_ptr, S.col_idx, S.val, 8, S.U0, step=1e-3, max_iter=13) as s:
+        info = s.solve()
+        assert info.iter == 13 and info.stop_reason == 1
+        again = s.solve()
+        assert again.iter == 13
+        more = s.step(2)          # fc_step ignores the solve budget
+        assert more.iter == 15
+        t = [1.0]
+        for _ in range(16):
+            t.append((1 + math.sqrt(1 + 4 * t[-1] ** 2)) / 2)
+        assert more.t == pytest.approx(t[15], rel=1e-14)
+
+
+def test_single_row_and_single_cluster(fc):
+    rp = np.array([0, 0], dtype=np.int64)
+    ci = np.zeros(0, dtype=np.int32)
+    v = np.zeros(0)
+    U0 = np.array([[0.2, 0.3, 0.5]])
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, 3, "fp64", 3, step=0.1)
+    ref = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=3, step=0.1)
+    assert np.abs(U - ref.X).max() <= 1e-14
+    wl = W.er_planted(500, 1, 6.0, 0.05, 9, val_dtype=torch.float64, u_dtype=torch.float64)
+    rp, ci, v, U0 = wl.numpy()
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, 1, "fp64", 3, step=0.1)
+    assert np.array_equal(U, np.ones_like(U))
+
+
+def test_nonfinite_start_is_reported(fc):
+    wl = W.er_planted(300, 4, 6.0, 0.05, 10)
+    U0 = wl.U0.clone()
+    U0[3, 1] = float("nan")
+    S = wl.to("cuda")
+    from paper_2506_04045_amd import _native
+    with pytest.raises(_native.FcError) as e:
+        fc.Solver(S.row_ptr, S.col_idx, S.val, 4, U0.cuda(), step=1e-3)
+    assert e.value.status == _native.FC_ERR_NONFINITE
+
+
+def test_validation_rejects_bad_matrices(fc):
+    from paper_2506_04045_amd import _native
+    A = np.array([[0, 1, 0], [0.5, 0, 1], [0, 1, 0]], dtype=float)   # not symmetric
+    rp, ci, v = pins.csr_from_dense(A)
+    Sd = csr_to_dev(rp, ci, v, torch.float32)
+    with pytest.raises(_native.FcError) as e:
+        fc.Solver(*Sd, 2, None, validate=True, step=0.1)
+    assert e.value.status == _native.FC_ERR_NOT_SYMMETRIC
+    B = np.array([[1, 1, 0], [1, 0, 1], [0, 1, 0]], dtype=float)     # stored diagonal
+    rp, ci, v = pins.csr_from_dense(B)
+    with pytest.raises(_native.FcError) as e:
+        fc.Solver(*csr_to_dev(rp, ci, v, torch.float32), 2, None, validate=True, step=0.1)
+    assert e.value.status == _native.FC_ERR_INVALID_ARG
+    with fc.Solver(*csr_to_dev(rp, ci, v, torch.float32), 2, None, validate=True, diag="stored",
+                   step=0.1) as s:
+        assert s.step(2).iter == 2
