@@ -1,0 +1,213 @@
+#!/usr/bin/env python3
+"""Throughput of accelerated gradient projection (Alg. 4) on one MI355X.
+
+Default workload: n = 70,000,000 articles, c = 32 clusters, power-law
+similarity (Chung-Lu pattern, degree exponent 2.1, mean degree 20, max
+50,000, ~1.4e9 stored nonzeros), planted overlapping communities with
+noise sigma 0.05, FP32 values and iterates, unit diagonal, FISTA with the
+constant step 1/L of Theorem 3.1.  One step = one iteration: the fused
+extrapolation/gradient/projection/Gram kernel, the sparse product of the new
+iterate with the loss terms, the reductions and the controller.
+
+Prints one JSON line (progress goes to stderr).  Inputs are generated on the
+GPU and resident in HBM before the timed region starts.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "APG iters/s + HBM GB/s at n=70M,c=32; served solves/s, p99 vs plain FP32"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SRC = os.path.join(ROOT, "paper_2506_04045_amd", "csrc", "fc_kernels.hpp")
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def log(msg: str) -> None:
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_sha() -> str:
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def algorithmic_bytes(n: int, c: int, nnz: int, precision: str) -> dict:
+    """Bytes each launch must move at least (index 4 B, row pointer 8 B)."""
+    b_val = {"fp32": 4, "fp64": 8, "mixed": 2}[precision]
+    b_u = {"fp32": 4, "fp64": 8, "mixed": 2}[precision]
+    b_z = 8 if precision == "fp64" else 4
+    b_x = 8 if precision == "fp64" else 4
+    spmm = 8 * (n + 1) + nnz * (4 + b_val) + n * c * b_u + n * c * b_z
+    fused = 2 * n * c * b_x + 2 * n * c * b_z + n * c * b_x
+    if precision == "mixed":
+        fused += n * c * 2
+    return {"spmm": spmm, "fused": fused}
+
+
+def measured_traffic(kernel: str, workload_key: str):
+    """HBM bytes per launch from the committed counter summary, or None when
+    the kernel source changed since the counters were taken."""
+    path = os.path.join(PROFILES, "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+        ent = data[workload_key][kernel]
+    except (KeyError, ValueError):
+        return None
+    if ent.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(args, c: int, n_full: int, nnz_full: int) -> dict:
+    """The FP64 oracle (plain C + OpenMP) timed for a few FISTA iterations on
+    a bounded sample: an instance of the same generator with fewer nodes, its
+    per-iteration time scaled to the full instance by the nonzero count."""
+    import torch
+    import oracle
+    import workloads as W
+    oracle.build(force=False)
+    ns = args.cpu_sample_n
+    log(f"cpu baseline: generating a {ns}-node sample instance on the host")
+    wl = W.chung_lu_planted(ns, c, 20.0, 2.1, 50_000.0, 0.05, 1, device="cpu")
+    rp, ci, v, U0 = wl.numpy()
+    spec, _ = oracle.spectral_norm(rp, ci, v, True, max_iter=200, rtol=1e-6)
+    tau = 1.0 / oracle.lipschitz_bound(spec, ns)
+    iters = args.cpu_iters
+    log(f"cpu baseline: {iters} oracle iterations on {oracle.num_threads()} threads")
+    t0 = time.perf_counter()
+    oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=iters, step=tau)
+    dt = (time.perf_counter() - t0) / iters
+    scale = nnz_full / max(1, wl.nnz)
+    del wl, rp, ci, v, U0
+    return {"value": 1.0 / (dt * scale), "unit": "iters/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": (f"FP64 oracle FISTA iterations ({iters}) on a {ns:,}-node instance of the "
+                       f"same power-law generator (c={c}, mean degree 20, exponent 2.1); "
+                       f"{dt:.3f} s/iteration scaled by nnz x{scale:.1f} to the full instance")}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__,
+                                 formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--n", type=int, default=70_000_000)
+    ap.add_argument("--c", type=int, default=32)
+    ap.add_argument("--precision", choices=["fp32", "mixed"], default="fp32")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-n", type=int, default=1_000_000)
+    ap.add_argument("--cpu-iters", type=int, default=2)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the solver is built and measured on a single "
+              "MI355X; multi-GPU runs are not part of this build (--gpus must be 1)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    import paper_2506_04045_amd as fc
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    log(f"library {fc.library_path()}")
+    t0 = time.perf_counter()
+    log(f"generating the power-law workload n={args.n:,} c={args.c} on the GPU")
+    wl = W.chung_lu_planted(args.n, args.c, 20.0, 2.1, 50_000.0, 0.05, args.seed, device="cuda")
+    torch.cuda.synchronize()
+    log(f"generated nnz={wl.nnz:,} (mean degree {wl.meta['realised_mean_deg']:.2f}, max "
+        f"{wl.meta['realised_max_deg']:,}) in {time.perf_counter() - t0:.1f} s")
+
+    prec = args.precision
+    t0 = time.perf_counter()
+    solver = fc.Solver(wl.row_ptr, wl.col_idx, wl.val, args.c, wl.U0, precision=prec,
+                       accelerate=True, step=0.0)
+    torch.cuda.synchronize()
+    log(f"solver created in {time.perf_counter() - t0:.1f} s")
+
+    info = solver.step(args.warmup)
+    log(f"warmup {args.warmup} iterations done, f={info.f:.6e}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info, kt = solver.step_profiled(args.steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"timed {args.steps} iterations in {elapsed:.3f} s, f={info.f:.6e}")
+    hist = solver.history()
+    f0, f_end = float(hist["f"][0]), float(info.f)
+    tau = float(hist["tau"][1])
+    solver.close()
+
+    n, c, nnz = wl.n, args.c, wl.nnz
+    launches = max(1, kt["launches"])
+    avg = {k: kt[f"{k}_ms"] / launches for k in ("fused", "spmm", "reduce", "control")}
+    alg = algorithmic_bytes(n, c, nnz, prec)
+    kernels = {}
+    for k in ("spmm", "fused"):
+        gbs = alg[k] / (avg[k] * 1e-3) / 1e9
+        kernels[k] = {"avg_ms": avg[k], "algorithmic_bytes": alg[k], "achieved_GBps": gbs,
+                      "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    kernels["reduce"] = {"avg_ms": avg["reduce"]}
+    kernels["control"] = {"avg_ms": avg["control"]}
+    dom = max(("spmm", "fused"), key=lambda k: avg[k])
+    wkey = f"powerlaw_n{n}_c{c}_{prec}"
+    traffic = measured_traffic(dom, wkey)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["achieved_GBps"],
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": kernels[dom]["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        del wl
+        torch.cuda.empty_cache()
+        cpu = cpu_baseline(args, c, n, nnz)
+        log(f"cpu baseline {cpu['value']:.3e} iters/s on {cpu['cores']} threads")
+
+    value = args.steps / elapsed
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == "fp32" else "f32+bf16/f16 storage",
+        "data": "synthetic",
+        "config": {
+            "workload": (f"power-law fuzzy clustering n={n:,} c={c}: Chung-Lu pattern "
+                         f"(exponent 2.1, mean degree 20, max 50,000), {nnz:,} stored nnz, "
+                         f"planted communities sigma 0.05, unit diagonal, FISTA constant step "
+                         f"1/L (Theorem 3.1), {prec}"),
+            "n": n, "c": c, "nnz": nnz, "precision": prec, "tau": tau,
+            "f0": f0, "f_end": f_end,
+        },
+        "kernels": kernels,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -154,6 +154,16 @@ void fc_options_default(fc_options *opt);
 fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0,
                     fc_dtype u0_dtype, void *stream, fc_solver **out);
 
+/* Device time per kernel of the launches made by fc_step_profiled. */
+typedef struct {
+    double fused_ms;    /* extrapolation, gradient, step, projection and Grams */
+    double spmm_ms;     /* sparse product S Xbar of the trial point */
+    double reduce_ms;   /* the fixed-order reductions of the partial sums */
+    double control_ms;  /* the one-workgroup controller */
+    int32_t launches;   /* trials launched (one launch of each kernel per trial) */
+    int32_t reserved;
+} fc_kernel_times;
+
 /* Run exactly `iters` more accepted iterations of Alg. 4 (Alg. 2/3 when
  * accelerate = 0) unless a stop rule fires first.  One iteration: the
  * extrapolated point Y_n, the gradient -4 (S Y_n - Y_n Y_n^T Y_n) of
@@ -162,6 +172,12 @@ fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0,
  * *info (may be NULL).  Returns FC_ERR_NONFINITE or FC_ERR_STEP when the
  * iteration failed; the handle then holds the last good iterate. */
 fc_status fc_step(fc_solver *h, int32_t iters, fc_info *info);
+
+/* fc_step with HIP events recorded on the solver's stream between the
+ * kernels of every trial; *times receives the summed device time per kernel
+ * (for measurement: the events add a few microseconds per trial). */
+fc_status fc_step_profiled(fc_solver *h, int32_t iters, fc_info *info,
+                           fc_kernel_times *times);
 
 /* Iterate until a stop rule fires or max_iter accepted iterations are
  * done (counted from fc_create).  Same errors as fc_step. */

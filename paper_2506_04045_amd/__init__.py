@@ -141,6 +141,17 @@ class Solver:
         N.check(N.load().fc_step(self._handle(), int(iters), ctypes.byref(info)))
         return Info.of(info)
 
+    def step_profiled(self, iters: int):
+        """fc_step_profiled: (Info, per-kernel device milliseconds summed over
+        the trials launched)."""
+        info = N.Info()
+        t = N.KernelTimes()
+        N.check(N.load().fc_step_profiled(self._handle(), int(iters), ctypes.byref(info),
+                                          ctypes.byref(t)))
+        return Info.of(info), dict(fused_ms=t.fused_ms, spmm_ms=t.spmm_ms,
+                                   reduce_ms=t.reduce_ms, control_ms=t.control_ms,
+                                   launches=t.launches)
+
     def solve(self) -> Info:
         info = N.Info()
         N.check(N.load().fc_solve(self._handle(), ctypes.byref(info)))

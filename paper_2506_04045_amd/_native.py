@@ -26,7 +26,7 @@ STATUS_NAMES = {0: "FC_OK", 1: "FC_ERR_INVALID_ARG", 2: "FC_ERR_UNSUPPORTED",
                 6: "FC_ERR_STEP", 7: "FC_ERR_NOT_SYMMETRIC"}
 
 EXPORTED = [
-    "fc_options_default", "fc_create", "fc_step", "fc_solve", "fc_get_u", "fc_get_history",
+    "fc_options_default", "fc_create", "fc_step", "fc_step_profiled", "fc_solve", "fc_get_u", "fc_get_history",
     "fc_get_state", "fc_set_state", "fc_destroy", "fc_objective", "fc_project", "fc_spmm",
     "fc_gram", "fc_spectral_norm", "fc_last_error",
 ]
@@ -58,6 +58,12 @@ class Info(ctypes.Structure):
                 ("pgrad_rel", ctypes.c_double)]
 
 
+class KernelTimes(ctypes.Structure):
+    _fields_ = [("fused_ms", ctypes.c_double), ("spmm_ms", ctypes.c_double),
+                ("reduce_ms", ctypes.c_double), ("control_ms", ctypes.c_double),
+                ("launches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -80,6 +86,8 @@ def load() -> ctypes.CDLL:
     lib.fc_create.restype = st
     lib.fc_step.argtypes = [P, i32, ctypes.POINTER(Info)]
     lib.fc_step.restype = st
+    lib.fc_step_profiled.argtypes = [P, i32, ctypes.POINTER(Info), ctypes.POINTER(KernelTimes)]
+    lib.fc_step_profiled.restype = st
     lib.fc_solve.argtypes = [P, ctypes.POINTER(Info)]
     lib.fc_solve.restype = st
     lib.fc_get_u.argtypes = [P, P, ctypes.c_int]

@@ -348,8 +348,61 @@ template <typename T> struct AccumOf { typedef T type; };
 template <> struct AccumOf<__hip_bfloat16> { typedef float type; };
 
 // TU: type of the gathered rows (f64, f32 or bf16); TZ: output type;
+// Sum over the nonzeros e in [beg, end) of a row: a team of SLOTS slots takes
+// SLOTS * DEPTH nonzeros per pass, and every slot issues its DEPTH gathers
+// (predicated on e < end) before it consumes any of them, so a row shorter
+// than one pass costs a single memory round trip.
+template <typename TU, typename VS, int CP, int DEPTH, typename TA, int NE>
+__device__ __forceinline__ void team_row_sum(const int32_t *__restrict__ col,
+                                             const VS *__restrict__ val,
+                                             const TU *__restrict__ U, int64_t beg, int64_t end,
+                                             int slot, int sub, TA (&acc)[NE]) {
+    using Cfg = SpmmCfg<TU, CP>;
+    for (int64_t e0 = beg + slot; e0 < end; e0 += DEPTH * Cfg::SLOTS) {
+        TA s[DEPTH];
+        TA g[DEPTH][NE];
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u) {
+            const int64_t e = e0 + u * Cfg::SLOTS;
+            s[u] = (TA)0;
+#pragma unroll
+            for (int q = 0; q < NE; ++q)
+                g[u][q] = (TA)0;
+            if (e < end) {
+                const int64_t j = col[e];
+                s[u] = (TA)to_f32(val[e]);
+                GatherLoad<TU, NE>::load(U + j * CP + sub * NE, g[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u)
+#pragma unroll
+            for (int q = 0; q < NE; ++q)
+                acc[q] += s[u] * g[u][q];
+    }
+}
+
+// Add the accumulators of the SLOTS slots of a team (lanes with equal sub).
+template <int GS, int TEAM, typename TA, int NE>
+__device__ __forceinline__ void team_slot_sum(TA (&acc)[NE]) {
+#pragma unroll
+    for (int off = GS; off < TEAM; off <<= 1)
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            if constexpr (sizeof(TA) == 8)
+                acc[q] += shfl_xor_d(acc[q], off);
+            else
+                acc[q] += shfl_xor_f(acc[q], off);
+        }
+}
+
 // TX: type of the row u_i used by the epilogue (the master copy);
 // VS: type of the stored values.
+//
+// Rows longer than heavy_thr nonzeros are not summed here: they are cut into
+// chunks (chunk_row, chunk_beg, chunk_len), each chunk is summed by one team
+// after the light rows, and k_spmm_combine adds the chunk sums of each heavy
+// row in chunk order.
 template <typename TU, typename TZ, typename TX, typename VS, int CP>
 __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ row_ptr,
                                               const int32_t *__restrict__ col,
@@ -358,10 +411,17 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ row_pt
                                               const TX *const *__restrict__ Xring,
                                               TZ *const *__restrict__ Zring, int64_t n,
                                               int diag_unit, double *__restrict__ trace_part,
-                                              const DevState *__restrict__ st, int role) {
+                                              const DevState *__restrict__ st, int role,
+                                              int64_t heavy_thr,
+                                              const int32_t *__restrict__ chunk_row,
+                                              const int64_t *__restrict__ chunk_beg,
+                                              const int32_t *__restrict__ chunk_len,
+                                              int64_t nchunks,
+                                              typename AccumOf<TU>::type *__restrict__ chunk_sum) {
     using Cfg = SpmmCfg<TU, CP>;
     using TA = typename AccumOf<TU>::type;
     constexpr int NE = Cfg::LANE_ELEMS;
+    constexpr int DEPTH = 4;
     if (st && !st->active)
         return;
     const int slot_role = st ? st->role[role] : 0;
@@ -380,48 +440,15 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ row_pt
 #pragma unroll
         for (int q = 0; q < NE; ++q)
             acc[q] = (TA)0;
-        const bool live = row < n;
+        bool live = row < n;
         if (live) {
             const int64_t beg = row_ptr[row], end = row_ptr[row + 1];
-            int64_t e = beg + slot;
-            for (; e + 3 * Cfg::SLOTS < end; e += 4 * Cfg::SLOTS) {
-                int64_t j[4];
-                TA s[4];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    j[u] = col[e + u * Cfg::SLOTS];
-                    s[u] = (TA)to_f32(val[e + u * Cfg::SLOTS]);
-                }
-                TA g[4][NE];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    GatherLoad<TU, NE>::load(U + j[u] * CP + sub * NE, g[u]);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int q = 0; q < NE; ++q)
-                        acc[q] += s[u] * g[u][q];
-            }
-            for (; e < end; e += Cfg::SLOTS) {
-                const int64_t j = col[e];
-                const TA s = (TA)to_f32(val[e]);
-                TA g[NE];
-                GatherLoad<TU, NE>::load(U + j * CP + sub * NE, g);
-#pragma unroll
-                for (int q = 0; q < NE; ++q)
-                    acc[q] += s * g[q];
-            }
+            if (end - beg > heavy_thr)
+                live = false;
+            else
+                team_row_sum<TU, VS, CP, DEPTH>(col, val, U, beg, end, slot, sub, acc);
         }
-        // sum the slots of the team (lanes with the same sub index)
-#pragma unroll
-        for (int off = Cfg::GS; off < Cfg::TEAM; off <<= 1)
-#pragma unroll
-            for (int q = 0; q < NE; ++q) {
-                if constexpr (sizeof(TA) == 8)
-                    acc[q] += shfl_xor_d(acc[q], off);
-                else
-                    acc[q] += shfl_xor_f(acc[q], off);
-            }
+        team_slot_sum<Cfg::GS, Cfg::TEAM>(acc);
         double d = 0.0;
         if (live && slot == 0) {
             TA xi[NE];
@@ -444,7 +471,69 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ row_pt
         if (live && slot == 0 && sub == 0)
             trace_acc += d;
     }
+    // chunks of heavy rows
+    constexpr int TEAMS = 256 / Cfg::TEAM;
+    for (int64_t k = (int64_t)blockIdx.x * TEAMS + team; k < nchunks; k += (int64_t)gridDim.x * TEAMS) {
+        TA acc[NE];
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            acc[q] = (TA)0;
+        const int64_t beg = chunk_beg[k];
+        team_row_sum<TU, VS, CP, DEPTH>(col, val, U, beg, beg + chunk_len[k], slot, sub, acc);
+        team_slot_sum<Cfg::GS, Cfg::TEAM>(acc);
+        if (slot == 0)
+#pragma unroll
+            for (int q = 0; q < NE; ++q)
+                chunk_sum[k * CP + sub * NE + q] = acc[q];
+        (void)chunk_row;
+    }
     __shared__ double sh[256];
+    sh[tid] = trace_acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (tid < s)
+            sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    if (tid == 0)
+        trace_part[blockIdx.x] = sh[0];
+}
+
+// Heavy rows: z_i = sum of the row's chunk sums in chunk order (+ u_i for the
+// unit diagonal), and the terms <u_i, z_i>.  One thread per component of a
+// row, 256/CP rows per workgroup step; partials go to trace_part[blockIdx].
+template <typename TA, typename TZ, typename TX, int CP>
+__global__ __launch_bounds__(256) void k_spmm_combine(const int32_t *__restrict__ heavy_rows,
+                                                      const int32_t *__restrict__ heavy_chunk_ptr,
+                                                      int64_t nheavy,
+                                                      const TA *__restrict__ chunk_sum,
+                                                      const TX *const *__restrict__ Xring,
+                                                      TZ *const *__restrict__ Zring, int diag_unit,
+                                                      double *__restrict__ trace_part,
+                                                      const DevState *__restrict__ st, int role) {
+    constexpr int RPB = 256 / CP;
+    if (st && !st->active)
+        return;
+    const int slot_role = st ? st->role[role] : 0;
+    const TX *__restrict__ X = Xring[slot_role];
+    TZ *__restrict__ Z = Zring[slot_role];
+    const int tid = threadIdx.x, k = tid % CP, rl = tid / CP;
+    __shared__ double sh[256];
+    double trace_acc = 0.0;
+    for (int64_t h0 = (int64_t)blockIdx.x * RPB; h0 < nheavy; h0 += (int64_t)gridDim.x * RPB) {
+        const int64_t h = h0 + rl;
+        if (h < nheavy) {
+            const int64_t row = heavy_rows[h];
+            TA acc = (TA)0;
+            for (int32_t q = heavy_chunk_ptr[h]; q < heavy_chunk_ptr[h + 1]; ++q)
+                acc += chunk_sum[(int64_t)q * CP + k];
+            const TA xi = (TA)X[row * CP + k];
+            if (diag_unit)
+                acc += xi;
+            Z[row * CP + k] = (TZ)acc;
+            trace_acc += (double)acc * (double)xi;
+        }
+    }
     sh[tid] = trace_acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {

@@ -103,6 +103,99 @@ void launch_reduce(const double *in, int64_t np, int64_t ld, int64_t ne, double 
     hipLaunchKernelGGL(k_reduce_cols, dim3(blocks), dim3(256), 0, s, in, np, ld, ne, out, eb);
 }
 
+// Rows with more than HEAVY_THR nonzeros are summed in chunks of HEAVY_CHUNK
+// nonzeros by whole teams and combined per row in chunk order.
+constexpr int64_t HEAVY_THR = 2048;
+constexpr int64_t HEAVY_CHUNK = 2048;
+
+// Heavy-row plan built on the host from row_ptr.  Device arrays are owned
+// by `bufs` (stream-ordered frees).
+struct HeavyPlan {
+    int64_t nheavy = 0, nchunks = 0;
+    int32_t *rows = nullptr, *chunk_ptr = nullptr, *chunk_row = nullptr, *chunk_len = nullptr;
+    int64_t *chunk_beg = nullptr;
+    void *chunk_sum = nullptr;
+    std::vector<void *> bufs;
+    hipStream_t s = nullptr;
+    ~HeavyPlan() {
+        for (void *p : bufs)
+            (void)hipFreeAsync(p, s);
+    }
+    template <typename P> hipError_t alloc(P **p, size_t bytes) {
+        void *q = nullptr;
+        hipError_t e = hipMallocAsync(&q, bytes > 0 ? bytes : 16, s);
+        if (e == hipSuccess) {
+            bufs.push_back(q);
+            *p = (P *)q;
+        }
+        return e;
+    }
+};
+
+fc_status build_heavy_plan(const int64_t *d_row_ptr, int64_t n, size_t acc_bytes, int cp,
+                           hipStream_t s, HeavyPlan &plan) {
+    plan.s = s;
+    std::vector<int64_t> rp(n + 1);
+    HIPCHK(hipMemcpyAsync(rp.data(), d_row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    std::vector<int32_t> rows, cptr, crow, clen;
+    std::vector<int64_t> cbeg;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t len = rp[i + 1] - rp[i];
+        if (len <= HEAVY_THR)
+            continue;
+        rows.push_back((int32_t)i);
+        cptr.push_back((int32_t)cbeg.size());
+        for (int64_t b = rp[i]; b < rp[i + 1]; b += HEAVY_CHUNK) {
+            const int64_t l = rp[i + 1] - b < HEAVY_CHUNK ? rp[i + 1] - b : HEAVY_CHUNK;
+            crow.push_back((int32_t)i);
+            cbeg.push_back(b);
+            clen.push_back((int32_t)l);
+        }
+    }
+    cptr.push_back((int32_t)cbeg.size());
+    plan.nheavy = (int64_t)rows.size();
+    plan.nchunks = (int64_t)cbeg.size();
+    if (plan.nheavy == 0)
+        return FC_OK;
+    HIPCHK(plan.alloc(&plan.rows, sizeof(int32_t) * rows.size()));
+    HIPCHK(plan.alloc(&plan.chunk_ptr, sizeof(int32_t) * cptr.size()));
+    HIPCHK(plan.alloc(&plan.chunk_row, sizeof(int32_t) * crow.size()));
+    HIPCHK(plan.alloc(&plan.chunk_len, sizeof(int32_t) * clen.size()));
+    HIPCHK(plan.alloc(&plan.chunk_beg, sizeof(int64_t) * cbeg.size()));
+    HIPCHK(plan.alloc(&plan.chunk_sum, acc_bytes * cp * cbeg.size()));
+    HIPCHK(hipMemcpyAsync(plan.rows, rows.data(), sizeof(int32_t) * rows.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(plan.chunk_ptr, cptr.data(), sizeof(int32_t) * cptr.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(plan.chunk_row, crow.data(), sizeof(int32_t) * crow.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(plan.chunk_len, clen.data(), sizeof(int32_t) * clen.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(plan.chunk_beg, cbeg.data(), sizeof(int64_t) * cbeg.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return FC_OK;
+}
+
+int combine_grid(int64_t nheavy, int cp) {
+    if (nheavy == 0)
+        return 0;
+    return grid_1d(nheavy, 256 / cp, 1024);
+}
+
+// Sparse product of the ring slot `role` (or slot 0 without a state) with
+// the heavy-row plan, writing g_spmm + g_comb trace partials.
+template <typename TU, typename TZ, typename TX, typename VS, int CP>
+void launch_spmm(const int64_t *row_ptr, const int32_t *col, const VS *val, const TU *const *Ur,
+                 const TX *const *Xr, TZ *const *Zr, int64_t n, int diag_unit, double *trace_part,
+                 int g_spmm, const DevState *st, int role, const HeavyPlan &hp, hipStream_t s) {
+    using TA = typename AccumOf<TU>::type;
+    hipLaunchKernelGGL((k_spmm<TU, TZ, TX, VS, CP>), dim3(g_spmm), dim3(256), 0, s, row_ptr, col, val,
+                       Ur, Xr, Zr, n, diag_unit, trace_part, st, role,
+                       hp.nheavy > 0 ? HEAVY_THR : INT64_MAX, hp.chunk_row, hp.chunk_beg,
+                       hp.chunk_len, hp.nchunks, (TA *)hp.chunk_sum);
+    if (hp.nheavy > 0)
+        hipLaunchKernelGGL((k_spmm_combine<TA, TZ, TX, CP>), dim3(combine_grid(hp.nheavy, CP)),
+                           dim3(256), 0, s, hp.rows, hp.chunk_ptr, hp.nheavy, (const TA *)hp.chunk_sum,
+                           Xr, Zr, diag_unit, trace_part + g_spmm, st, role);
+}
+
 // Dispatch a functor on the padded width CP in {4, 8, 16, 32, 64}.
 template <typename F> fc_status with_cp(int cp, F &&f) {
     switch (cp) {
@@ -248,7 +341,8 @@ struct fc_solver {
     double *d_GY64 = nullptr;
     void *d_GYs = nullptr;
     double *d_part_fused = nullptr, *d_part_spmm = nullptr, *d_part_gram = nullptr;
-    int g_fused = 1, g_spmm = 1, g_gram = 1;
+    int g_fused = 1, g_spmm = 1, g_gram = 1, g_comb = 0;
+    HeavyPlan heavy;
     double *d_red_mats = nullptr, *d_red_trace = nullptr;
     double *d_sched = nullptr;
     int sched_len = 0;
@@ -282,7 +376,7 @@ int fused_ne(int cpm) { return 3 * cpm * cpm + FUSED_NSCAL; }
 // Launch one trial: fused step -> sparse product of the trial point ->
 // reductions -> controller.
 template <typename T, typename TU, typename VS, int CP>
-fc_status launch_trial_t(fc_solver *h) {
+fc_status launch_trial_t(fc_solver *h, hipEvent_t *ev) {
     constexpr int CPM = CP < 16 ? 16 : CP;
     using Cfg = SpmmCfg<TU, CP>;
     hipStream_t s = h->stream;
@@ -291,6 +385,8 @@ fc_status launch_trial_t(fc_solver *h) {
     auto Zr = (T *const *)h->d_Zring;
     auto Sr = (__hip_bfloat16 *const *)h->d_Sring;
     auto GYs = (const T *)h->d_GYs;
+    if (ev)
+        HIPCHK(hipEventRecord(ev[0], s));
 #define FUSED_LAUNCH(A, B, SH)                                                                 \
     hipLaunchKernelGGL((k_fused<T, CP, A, B, SH>), dim3(h->g_fused), dim3(256), 0, s, Xr, Zr, Sr, \
                        GYs, h->n, h->c, h->d_part_fused, (const DevState *)h->d_state)
@@ -313,18 +409,26 @@ fc_status launch_trial_t(fc_solver *h) {
         else FUSED_LAUNCH(false, false, false);
     }
 #undef FUSED_LAUNCH
+    if (ev)
+        HIPCHK(hipEventRecord(ev[1], s));
     const TU *const *Ur = shadow ? (const TU *const *)h->d_Sring : (const TU *const *)h->d_Xring;
-    hipLaunchKernelGGL((k_spmm<TU, T, T, VS, CP>), dim3(h->g_spmm), dim3(256), 0, s, h->row_ptr,
-                       h->col, (const VS *)h->val, Ur, (const T *const *)h->d_Xring, Zr, h->n,
-                       (int)(h->diag == FC_DIAG_UNIT), h->d_part_spmm,
-                       (const DevState *)h->d_state, (int)ROLE_N);
+    launch_spmm<TU, T, T, VS, CP>(h->row_ptr, h->col, (const VS *)h->val, Ur,
+                                  (const T *const *)h->d_Xring, Zr, h->n,
+                                  (int)(h->diag == FC_DIAG_UNIT), h->d_part_spmm, h->g_spmm,
+                                  (const DevState *)h->d_state, (int)ROLE_N, h->heavy, s);
+    if (ev)
+        HIPCHK(hipEventRecord(ev[2], s));
     const int ne = fused_ne(CPM);
     launch_reduce(h->d_part_fused, h->g_fused, ne, ne, h->d_red_mats, s);
-    launch_reduce(h->d_part_spmm, h->g_spmm, 1, 1, h->d_red_trace, s);
+    launch_reduce(h->d_part_spmm, h->g_spmm + h->g_comb, 1, 1, h->d_red_trace, s);
+    if (ev)
+        HIPCHK(hipEventRecord(ev[3], s));
     hipLaunchKernelGGL((k_control<T, CPM>), dim3(1), dim3(256), 0, s, h->d_state, 1,
                        (const double *)h->d_red_mats, (const double *)h->d_red_trace, h->d_GY64,
                        (T *)h->d_GYs, (const double *)h->d_sched, h->d_hist_f, h->d_hist_tau,
                        h->d_hist_trials, h->d_hist_r);
+    if (ev)
+        HIPCHK(hipEventRecord(ev[4], s));
     (void)Cfg::TEAM;
     HIPCHK(hipGetLastError());
     return FC_OK;
@@ -344,12 +448,12 @@ fc_status launch_init_t(fc_solver *h) {
                            dim3(256), 0, s, (const float *)h->X[0], (__hip_bfloat16 *)h->shadow[0],
                            h->n * h->cp);
     const TU *const *Ur = shadow ? (const TU *const *)h->d_Sring : (const TU *const *)h->d_Xring;
-    hipLaunchKernelGGL((k_spmm<TU, T, T, VS, CP>), dim3(h->g_spmm), dim3(256), 0, s, h->row_ptr,
-                       h->col, (const VS *)h->val, Ur, (const T *const *)h->d_Xring,
-                       (T *const *)h->d_Zring, h->n, (int)(h->diag == FC_DIAG_UNIT),
-                       h->d_part_spmm, (const DevState *)h->d_state, (int)ROLE_C);
+    launch_spmm<TU, T, T, VS, CP>(h->row_ptr, h->col, (const VS *)h->val, Ur,
+                                  (const T *const *)h->d_Xring, (T *const *)h->d_Zring, h->n,
+                                  (int)(h->diag == FC_DIAG_UNIT), h->d_part_spmm, h->g_spmm,
+                                  (const DevState *)h->d_state, (int)ROLE_C, h->heavy, s);
     launch_reduce(h->d_part_gram, (int64_t)h->g_gram * 4, ld, ld, h->d_red_mats, s);
-    launch_reduce(h->d_part_spmm, h->g_spmm, 1, 1, h->d_red_trace, s);
+    launch_reduce(h->d_part_spmm, h->g_spmm + h->g_comb, 1, 1, h->d_red_trace, s);
     hipLaunchKernelGGL((k_control<T, CPM>), dim3(1), dim3(256), 0, s, h->d_state, 0,
                        (const double *)h->d_red_mats, (const double *)h->d_red_trace, h->d_GY64,
                        (T *)h->d_GYs, (const double *)h->d_sched, h->d_hist_f, h->d_hist_tau,
@@ -358,15 +462,15 @@ fc_status launch_init_t(fc_solver *h) {
     return FC_OK;
 }
 
-fc_status launch_trial(fc_solver *h) {
+fc_status launch_trial(fc_solver *h, hipEvent_t *ev = nullptr) {
     return with_cp(h->cp, [&](auto cpc) -> fc_status {
         constexpr int CP = decltype(cpc)::value;
         if (h->prec == FC_PREC_FP64)
-            return launch_trial_t<double, double, double, CP>(h);
+            return launch_trial_t<double, double, double, CP>(h, ev);
         if (h->prec == FC_PREC_FP32)
-            return launch_trial_t<float, float, float, CP>(h);
+            return launch_trial_t<float, float, float, CP>(h, ev);
         if constexpr (CP >= 8)
-            return launch_trial_t<float, __hip_bfloat16, __half, CP>(h);
+            return launch_trial_t<float, __hip_bfloat16, __half, CP>(h, ev);
         return fail(FC_ERR_UNSUPPORTED, "mixed precision needs c >= 5 (padded width >= 8)");
     });
 }
@@ -420,8 +524,48 @@ fc_status status_of(const fc_solver *h) {
     return FC_OK;
 }
 
+// Events of a profiled run: five per trial, released at the end.
+struct EventLog {
+    std::vector<hipEvent_t> ev;
+    fc_kernel_times *out = nullptr;
+    ~EventLog() {
+        for (hipEvent_t e : ev)
+            (void)hipEventDestroy(e);
+    }
+    hipError_t add_trial(hipEvent_t **slot) {
+        const size_t k = ev.size();
+        ev.resize(k + 5, nullptr);
+        for (size_t q = k; q < k + 5; ++q) {
+            hipError_t e = hipEventCreate(&ev[q]);
+            if (e != hipSuccess)
+                return e;
+        }
+        *slot = &ev[k];
+        return hipSuccess;
+    }
+    hipError_t collect() {
+        if (!out)
+            return hipSuccess;
+        std::memset(out, 0, sizeof(*out));
+        for (size_t k = 0; k + 5 <= ev.size(); k += 5) {
+            float ms[4];
+            for (int q = 0; q < 4; ++q) {
+                hipError_t e = hipEventElapsedTime(&ms[q], ev[k + q], ev[k + q + 1]);
+                if (e != hipSuccess)
+                    return e;
+            }
+            out->fused_ms += ms[0];
+            out->spmm_ms += ms[1];
+            out->reduce_ms += ms[2];
+            out->control_ms += ms[3];
+            out->launches += 1;
+        }
+        return hipSuccess;
+    }
+};
+
 // Run until `target` accepted iterations (or a stop) with the given budget.
-fc_status run_until(fc_solver *h, int32_t target, int32_t max_iter) {
+fc_status run_until(fc_solver *h, int32_t target, int32_t max_iter, EventLog *log = nullptr) {
     if (h->h.error != ERR_NONE)
         return status_of(h);
     h->h.target = target;
@@ -437,7 +581,10 @@ fc_status run_until(fc_solver *h, int32_t target, int32_t max_iter) {
         if (launches < 1)
             launches = 1;
         for (int k = 0; k < launches; ++k) {
-            st = launch_trial(h);
+            hipEvent_t *ev = nullptr;
+            if (log)
+                HIPCHK(log->add_trial(&ev));
+            st = launch_trial(h, ev);
             if (st != FC_OK)
                 return st;
         }
@@ -445,6 +592,8 @@ fc_status run_until(fc_solver *h, int32_t target, int32_t max_iter) {
         if (st != FC_OK)
             return st;
     }
+    if (log)
+        HIPCHK(log->collect());
     return status_of(h);
 }
 
@@ -622,9 +771,13 @@ fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_d
         });
         h->g_spmm = grid_1d(h->n, rows_per_wg, (int64_t)cus * 32);
     }
+    st = build_heavy_plan(S->row_ptr, S->n, h->prec == FC_PREC_FP64 ? 8 : 4, h->cp, s, h->heavy);
+    if (st != FC_OK)
+        return cleanup(st);
+    h->g_comb = combine_grid(h->heavy.nheavy, h->cp);
     const int ne = fused_ne(h->cpm);
     if (h->alloc(&h->d_part_fused, sizeof(double) * (size_t)h->g_fused * ne) != hipSuccess ||
-        h->alloc(&h->d_part_spmm, sizeof(double) * (size_t)h->g_spmm) != hipSuccess ||
+        h->alloc(&h->d_part_spmm, sizeof(double) * (size_t)(h->g_spmm + h->g_comb)) != hipSuccess ||
         h->alloc(&h->d_part_gram, sizeof(double) * (size_t)h->g_gram * 4 * h->cpm * h->cpm) != hipSuccess ||
         h->alloc(&h->d_red_mats, sizeof(double) * ne) != hipSuccess ||
         h->alloc(&h->d_red_trace, sizeof(double) * 2) != hipSuccess ||
@@ -750,6 +903,24 @@ fc_status fc_step(fc_solver *h, int32_t iters, fc_info *info) {
     return st;
 }
 
+fc_status fc_step_profiled(fc_solver *h, int32_t iters, fc_info *info, fc_kernel_times *times) {
+    g_last_error.clear();
+    if (!h || !times)
+        return fail(FC_ERR_INVALID_ARG, "solver or times is NULL");
+    if (iters < 0)
+        return fail(FC_ERR_INVALID_ARG, "iters < 0");
+    std::memset(times, 0, sizeof(*times));
+    fc_status st = FC_OK;
+    if (iters > 0) {
+        EventLog log;
+        log.out = times;
+        const int64_t target = (int64_t)h->h.iter + iters;
+        st = run_until(h, (int32_t)(target > INT_MAX ? INT_MAX : target), INT_MAX, &log);
+    }
+    fill_info(h, info);
+    return st;
+}
+
 fc_status fc_solve(fc_solver *h, fc_info *info) {
     g_last_error.clear();
     if (!h)
@@ -868,12 +1039,17 @@ fc_status spmm_and_gram_t(const fc_csr *S, fc_diag diag, const T *Upad, T *Zpad,
     HIPCHK(hipMemcpyAsync(ring.p, ptrs, sizeof(ptrs), hipMemcpyHostToDevice, s));
     const T *const *Ur = (const T *const *)ring.p;
     T *const *Zr = (T *const *)((void **)ring.p + 1);
-    HIPCHK(dev_alloc(part, sizeof(double) * g_spmm, s));
+    HeavyPlan hp;
+    fc_status st = build_heavy_plan(S->row_ptr, n, sizeof(T), CP, s, hp);
+    if (st != FC_OK)
+        return st;
+    const int g_comb = combine_grid(hp.nheavy, CP);
+    HIPCHK(dev_alloc(part, sizeof(double) * (g_spmm + g_comb), s));
     HIPCHK(dev_alloc(red, sizeof(double) * (1 + CPM * CPM), s));
-    hipLaunchKernelGGL((k_spmm<T, T, T, VS, CP>), dim3(g_spmm), dim3(256), 0, s, S->row_ptr,
-                       S->col_idx, (const VS *)S->values, Ur, Ur, Zr, n, (int)(diag == FC_DIAG_UNIT),
-                       (double *)part.p, (const DevState *)nullptr, 0);
-    launch_reduce((const double *)part.p, g_spmm, 1, 1, (double *)red.p, s);
+    launch_spmm<T, T, T, VS, CP>(S->row_ptr, S->col_idx, (const VS *)S->values, Ur, Ur, Zr, n,
+                                 (int)(diag == FC_DIAG_UNIT), (double *)part.p, g_spmm,
+                                 (const DevState *)nullptr, 0, hp, s);
+    launch_reduce((const double *)part.p, g_spmm + g_comb, 1, 1, (double *)red.p, s);
     DevBuf gpart;
     if (want_gram) {
         const int g_gram = grid_1d(cdiv(n, 16), 4, (int64_t)cus * 2);

@@ -255,3 +255,22 @@ def test_validation_rejects_bad_matrices(fc):
     with fc.Solver(*csr_to_dev(rp, ci, v, torch.float32), 2, None, validate=True, diag="stored",
                    step=0.1) as s:
         assert s.step(2).iter == 2
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_hub_rows_take_the_chunked_path(fc, prec):
+    """Rows longer than the chunk threshold (2,048 nonzeros) are summed in
+    chunks and combined per row; the solve must still follow the oracle."""
+    from tests.gpu_util import star_plus_er
+    rp, ci, v = star_plus_er(6000, 4.0, 12)
+    assert np.diff(rp).max() > 2 * 2048
+    n, c = 6000, 16
+    U0 = pins.random_simplex_rows(n, c, np.random.default_rng(12))
+    if prec == "fp32":
+        v = v.astype(np.float32).astype(np.float64)
+        U0 = U0.astype(np.float32).astype(np.float64)
+    ref = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=30, step=2e-4)
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, c, prec, 30, step=2e-4)
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    assert np.abs(U - ref.X).max() <= tol
+    assert abs(info.f - ref.f[-1]) <= tol * abs(ref.f[-1])

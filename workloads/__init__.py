@@ -133,7 +133,8 @@ def planted_communities(n: int, c: int, kmax: int, alpha: float, seed: int,
     # kmax distinct communities per node: the first kmax of a random permutation
     # (argsort of uniform keys); only the first k_i are used.
     keys = torch.rand(n, c, generator=g, device=device)
-    ids = torch.argsort(keys, dim=1)[:, :kmax]
+    ids = torch.argsort(keys, dim=1)[:, :kmax].contiguous()
+    del keys
     gam = _gamma(torch.full((n * kmax,), float(alpha), device=device), g).view(n, kmax)
     used = torch.arange(kmax, device=device).view(1, -1) < k.view(-1, 1)
     gam = torch.where(used, gam, torch.zeros_like(gam))
