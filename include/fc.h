@@ -197,10 +197,15 @@ fc_status fc_get_history(const fc_solver *h, int32_t cap, double *f_log,
                          double *step_log, int32_t *trials_log, double *r_log,
                          int32_t *count);
 
-/* Checkpoint: serialise the solver state (Xbar_n, Xbar_{n-1}, t, L, f, the
- * iteration counters) into host memory.  With buf = NULL, *bytes receives
- * the size needed.  fc_set_state restores a state taken from a solver with
- * the same S, n, c and options; the products S Xbar are recomputed. */
+/* Checkpoint: serialise the solver state (Xbar_n, Xbar_{n-1}, their
+ * products S Xbar, the Gram matrix of the next extrapolated point, t, L, f,
+ * the iteration counters and the history) into host memory `buf` of
+ * *bytes bytes.  With buf = NULL, *bytes receives the size needed; a
+ * smaller buffer is FC_ERR_INVALID_ARG.  fc_set_state restores a state taken
+ * from a solver built on the same S with the same n, c and options
+ * (FC_ERR_INVALID_ARG otherwise); iterating after a restore gives the same
+ * results, bit for bit, as iterating without the interruption.
+ * Both synchronise the solver's stream. */
 fc_status fc_get_state(const fc_solver *h, void *buf, size_t *bytes);
 fc_status fc_set_state(fc_solver *h, const void *buf, size_t bytes);
 

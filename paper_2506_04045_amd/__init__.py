@@ -177,6 +177,19 @@ class Solver:
         k = cnt.value
         return dict(f=f[:k].copy(), tau=tau[:k].copy(), trials=trials[:k].copy(), r=r[:k].copy())
 
+    def get_state(self) -> bytes:
+        """Checkpoint (fc_get_state) as a bytes object."""
+        size = ctypes.c_size_t(0)
+        N.check(N.load().fc_get_state(self._handle(), None, ctypes.byref(size)))
+        buf = ctypes.create_string_buffer(size.value)
+        N.check(N.load().fc_get_state(self._handle(), buf, ctypes.byref(size)))
+        return buf.raw[: size.value]
+
+    def set_state(self, state: bytes) -> None:
+        """Restore a checkpoint (fc_set_state)."""
+        buf = ctypes.create_string_buffer(state, len(state))
+        N.check(N.load().fc_set_state(self._handle(), buf, len(state)))
+
     def close(self) -> None:
         if self._h is not None:
             N.load().fc_destroy(self._h)

@@ -994,18 +994,137 @@ fc_status fc_get_history(const fc_solver *h, int32_t cap, double *f_log, double 
     return FC_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Checkpoint layout: header, then Xbar_c, Xbar_p, S Xbar_c, S Xbar_p
+// (n x CP each, padded layout), G_Y in double and in the compute type, and
+// the history of the first iter + 1 iterations.  Restoring all of these makes
+// a resumed run bitwise equal to an uninterrupted one.
+struct CkptHeader {
+    uint64_t magic;
+    uint32_t version;
+    uint32_t header_bytes;
+    int64_t n;
+    int32_t c, cp, prec, accelerate, backtrack, diag;
+    int32_t hist_len, reserved;
+    DevState st;
+};
+constexpr uint64_t CKPT_MAGIC = 0x3130545043434646ull;  // "FFCCPT01"
+
+size_t ckpt_bytes(const fc_solver *h, int32_t hist_len) {
+    const size_t esz = h->prec == FC_PREC_FP64 ? 8 : 4;
+    const size_t mat = (size_t)h->n * h->cp * esz;
+    const size_t g = (size_t)h->cpm * h->cpm;
+    return sizeof(CkptHeader) + 4 * mat + g * 8 + g * esz +
+           (size_t)hist_len * (3 * sizeof(double) + sizeof(int32_t));
+}
+
+}  // namespace
+
+extern "C" {
+
 fc_status fc_get_state(const fc_solver *h, void *buf, size_t *bytes) {
-    (void)h;
-    (void)buf;
-    (void)bytes;
-    return fail(FC_ERR_UNSUPPORTED, "checkpointing is not implemented yet");
+    g_last_error.clear();
+    if (!h || !bytes)
+        return fail(FC_ERR_INVALID_ARG, "solver or bytes is NULL");
+    int32_t hist_len = h->h.iter + 1 < h->hist_cap ? h->h.iter + 1 : h->hist_cap;
+    const size_t need = ckpt_bytes(h, hist_len);
+    if (!buf) {
+        *bytes = need;
+        return FC_OK;
+    }
+    if (*bytes < need)
+        return fail(FC_ERR_INVALID_ARG, "checkpoint buffer too small");
+    *bytes = need;
+    hipStream_t s = h->stream;
+    CkptHeader hd = {};
+    hd.magic = CKPT_MAGIC;
+    hd.version = 1;
+    hd.header_bytes = sizeof(CkptHeader);
+    hd.n = h->n;
+    hd.c = h->c;
+    hd.cp = h->cp;
+    hd.prec = (int32_t)h->prec;
+    hd.accelerate = h->accelerate;
+    hd.backtrack = h->backtrack;
+    hd.diag = (int32_t)h->diag;
+    hd.hist_len = hist_len;
+    hd.st = h->h;
+    char *p = (char *)buf;
+    std::memcpy(p, &hd, sizeof(hd));
+    p += sizeof(hd);
+    const size_t esz = h->prec == FC_PREC_FP64 ? 8 : 4;
+    const size_t mat = (size_t)h->n * h->cp * esz;
+    const void *src[4] = {h->X[h->h.role[ROLE_C]], h->X[h->h.role[ROLE_P]], h->Z[h->h.role[ROLE_C]],
+                          h->Z[h->h.role[ROLE_P]]};
+    for (int k = 0; k < 4; ++k, p += mat)
+        HIPCHK(hipMemcpyAsync(p, src[k], mat, hipMemcpyDeviceToHost, s));
+    const size_t g = (size_t)h->cpm * h->cpm;
+    HIPCHK(hipMemcpyAsync(p, h->d_GY64, g * 8, hipMemcpyDeviceToHost, s));
+    p += g * 8;
+    HIPCHK(hipMemcpyAsync(p, h->d_GYs, g * esz, hipMemcpyDeviceToHost, s));
+    p += g * esz;
+    HIPCHK(hipMemcpyAsync(p, h->d_hist_f, sizeof(double) * hist_len, hipMemcpyDeviceToHost, s));
+    p += sizeof(double) * hist_len;
+    HIPCHK(hipMemcpyAsync(p, h->d_hist_tau, sizeof(double) * hist_len, hipMemcpyDeviceToHost, s));
+    p += sizeof(double) * hist_len;
+    HIPCHK(hipMemcpyAsync(p, h->d_hist_r, sizeof(double) * hist_len, hipMemcpyDeviceToHost, s));
+    p += sizeof(double) * hist_len;
+    HIPCHK(hipMemcpyAsync(p, h->d_hist_trials, sizeof(int32_t) * hist_len, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return FC_OK;
 }
 
 fc_status fc_set_state(fc_solver *h, const void *buf, size_t bytes) {
-    (void)h;
-    (void)buf;
-    (void)bytes;
-    return fail(FC_ERR_UNSUPPORTED, "checkpointing is not implemented yet");
+    g_last_error.clear();
+    if (!h || !buf)
+        return fail(FC_ERR_INVALID_ARG, "solver or buffer is NULL");
+    if (bytes < sizeof(CkptHeader))
+        return fail(FC_ERR_INVALID_ARG, "checkpoint buffer too small");
+    CkptHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (hd.magic != CKPT_MAGIC || hd.version != 1 || hd.header_bytes != sizeof(CkptHeader))
+        return fail(FC_ERR_INVALID_ARG, "not a checkpoint of this library version");
+    if (hd.n != h->n || hd.c != h->c || hd.cp != h->cp || hd.prec != (int32_t)h->prec ||
+        hd.accelerate != h->accelerate || hd.backtrack != h->backtrack || hd.diag != (int32_t)h->diag)
+        return fail(FC_ERR_INVALID_ARG, "checkpoint was taken from a solver with other n, c or options");
+    if (hd.hist_len < 1 || hd.hist_len > h->hist_cap || bytes < ckpt_bytes(h, hd.hist_len))
+        return fail(FC_ERR_INVALID_ARG, "checkpoint buffer truncated");
+    hipStream_t s = h->stream;
+    const char *p = (const char *)buf + sizeof(CkptHeader);
+    const size_t esz = h->prec == FC_PREC_FP64 ? 8 : 4;
+    const size_t mat = (size_t)h->n * h->cp * esz;
+    void *dst[4] = {h->X[0], h->X[1], h->Z[0], h->Z[1]};
+    for (int k = 0; k < 4; ++k, p += mat)
+        HIPCHK(hipMemcpyAsync(dst[k], p, mat, hipMemcpyHostToDevice, s));
+    const size_t g = (size_t)h->cpm * h->cpm;
+    HIPCHK(hipMemcpyAsync(h->d_GY64, p, g * 8, hipMemcpyHostToDevice, s));
+    p += g * 8;
+    HIPCHK(hipMemcpyAsync(h->d_GYs, p, g * esz, hipMemcpyHostToDevice, s));
+    p += g * esz;
+    const int32_t hl = hd.hist_len;
+    HIPCHK(hipMemcpyAsync(h->d_hist_f, p, sizeof(double) * hl, hipMemcpyHostToDevice, s));
+    p += sizeof(double) * hl;
+    HIPCHK(hipMemcpyAsync(h->d_hist_tau, p, sizeof(double) * hl, hipMemcpyHostToDevice, s));
+    p += sizeof(double) * hl;
+    HIPCHK(hipMemcpyAsync(h->d_hist_r, p, sizeof(double) * hl, hipMemcpyHostToDevice, s));
+    p += sizeof(double) * hl;
+    HIPCHK(hipMemcpyAsync(h->d_hist_trials, p, sizeof(int32_t) * hl, hipMemcpyHostToDevice, s));
+    if (h->prec == FC_PREC_MIXED)
+        for (int k = 0; k < 2; ++k)
+            hipLaunchKernelGGL((k_convert<float, __hip_bfloat16>), dim3(grid_1d(h->n * h->cp, 256, 8192)),
+                               dim3(256), 0, s, (const float *)h->X[k], (__hip_bfloat16 *)h->shadow[k],
+                               h->n * h->cp);
+    HIPCHK(hipGetLastError());
+    DevState st = hd.st;
+    st.role[ROLE_C] = 0;
+    st.role[ROLE_P] = 1;
+    st.role[ROLE_N] = 2;
+    st.hist_cap = h->hist_cap;
+    h->h = st;
+    return write_state(h);
 }
 
 void fc_destroy(fc_solver *h) {

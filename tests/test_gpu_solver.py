@@ -274,3 +274,27 @@ def test_hub_rows_take_the_chunked_path(fc, prec):
     tol = 1e-9 if prec == "fp64" else 1e-4
     assert np.abs(U - ref.X).max() <= tol
     assert abs(info.f - ref.f[-1]) <= tol * abs(ref.f[-1])
+
+
+@pytest.mark.parametrize("backtrack", [False, True])
+def test_checkpoint_resume_is_bitwise(fc, backtrack):
+    wl = W.er_planted(4000, 16, 12.0, 0.05, 13)
+    S = wl.to("cuda")
+    kw = dict(backtrack=True, L0=10.0) if backtrack else dict(step=1e-3)
+    with fc.Solver(S.row_ptr, S.col_idx, S.val, 16, S.U0, **kw) as a:
+        a.step(25)
+        U_ref, f_ref = a.get_u().cpu().numpy(), a.info().f
+        h_ref = a.history()
+    with fc.Solver(S.row_ptr, S.col_idx, S.val, 16, S.U0, **kw) as b:
+        b.step(11)
+        state = b.get_state()
+    with fc.Solver(S.row_ptr, S.col_idx, S.val, 16, None, **kw) as c:
+        c.set_state(state)
+        assert c.info().iter == 11
+        c.step(14)
+        assert np.array_equal(c.get_u().cpu().numpy(), U_ref) and c.info().f == f_ref
+        assert np.array_equal(c.history()["f"], h_ref["f"])
+    from paper_2506_04045_amd import _native
+    with fc.Solver(S.row_ptr, S.col_idx, S.val, 8, None, step=1e-3) as d:
+        with pytest.raises(_native.FcError):
+            d.set_state(state)
