@@ -101,17 +101,67 @@ template <int CPM> struct FusedLayout {
 };
 
 // ---------------------------------------------------------------------------
+// One problem instance as the kernels see it: the similarity, the heavy-row
+// plan of the sparse product, the iterate/product rings, the device state
+// and the buffers of partial sums.  The kernels below are written as device
+// functions of (instance, block index, block count); thin wrappers run them
+// either for one instance (block index = blockIdx) or for a batch, where a
+// persistent grid walks a table of (instance, block) pairs.  Each instance's
+// blocks do the same work in both cases, so its results do not depend on
+// what it is batched with.
+// ---------------------------------------------------------------------------
+struct Inst {
+    const int64_t *row_ptr;
+    const int32_t *col;
+    const void *val;
+    int64_t n;
+    int32_t c;
+    int32_t diag_unit;
+    int64_t heavy_thr, nchunks, nheavy;
+    const int32_t *chunk_row;
+    const int64_t *chunk_beg;
+    const int32_t *chunk_len;
+    const int32_t *heavy_rows;
+    const int32_t *heavy_chunk_ptr;
+    void *chunk_sum;
+    void *X[3];   // iterate ring (compute type), padded n x CP
+    void *Z[3];   // products S X in the same slots
+    void *Sh[3];  // bfloat16 shadows of X (mixed precision)
+    DevState *st; // NULL: stateless use, ring slot 0
+    double *GY64;
+    void *GYs;
+    double *part_fused;
+    double *part_spmm;
+    double *red_mats;
+    int32_t g_fused, g_spmm, g_comb, g_red;
+    const double *sched;
+    double *hist_f, *hist_tau, *hist_r;
+    int32_t *hist_trials;
+};
+
+// One entry of a batch table: block `blk` of instance `inst`.
+struct VBlk {
+    int32_t inst;
+    int32_t blk;
+};
+
+__device__ __forceinline__ int ring_slot(const Inst &I, int role) {
+    return I.st ? I.st->role[role] : 0;
+}
+__device__ __forceinline__ bool inst_active(const Inst &I) { return !I.st || I.st->active; }
+
+// ---------------------------------------------------------------------------
 // Deterministic column reduction: out[e] = sum_p in[p * ld + e] for
 // e < ne, p < np.  A workgroup owns EB consecutive entries; its 256 threads
 // split the p range into 256/EB fixed chunks that are combined in order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_reduce_cols(const double *__restrict__ in, int64_t np,
-                                                     int64_t ld, int64_t ne,
-                                                     double *__restrict__ out, int eb) {
+__device__ __forceinline__ void reduce_cols_body(const double *__restrict__ in, int64_t np,
+                                                 int64_t ld, int64_t ne, double *__restrict__ out,
+                                                 int eb, int64_t blk) {
     __shared__ double sh[256];
     const int tid = threadIdx.x;
     const int el = tid % eb, chunk = tid / eb, nchunk = 256 / eb;
-    const int64_t e = (int64_t)blockIdx.x * eb + el;
+    const int64_t e = blk * eb + el;
     double acc = 0.0;
     if (e < ne) {
         const int64_t per = (np + nchunk - 1) / nchunk;
@@ -127,6 +177,37 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const double *__restrict__ 
         for (int k = 1; k < nchunk; ++k)
             s += sh[k * eb + el];
         out[e] = s;
+    }
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void k_reduce_cols(const double *__restrict__ in, int64_t np,
+                                                     int64_t ld, int64_t ne,
+                                                     double *__restrict__ out, int eb) {
+    reduce_cols_body(in, np, ld, ne, out, eb, blockIdx.x);
+}
+
+// The fused kernel's partial sums of one instance: entries split in blocks of
+// 64, each reduced over the instance's g_fused workgroup partials.
+template <int CPM>
+__device__ __forceinline__ void reduce_fused_body(const Inst &I, int64_t blk) {
+    constexpr int NE = FusedLayout<CPM>::NE;
+    reduce_cols_body(I.part_fused, I.g_fused, NE, NE, I.red_mats, 64, blk);
+}
+template <int CPM> __global__ __launch_bounds__(256) void k_reduce_fused_1(Inst I) {
+    if (inst_active(I))
+        reduce_fused_body<CPM>(I, blockIdx.x);
+}
+template <int CPM>
+__global__ __launch_bounds__(256) void k_reduce_fused_b(const Inst *__restrict__ insts,
+                                                        const VBlk *__restrict__ tab,
+                                                        const int32_t *__restrict__ count) {
+    for (int64_t vb = blockIdx.x; vb < *count; vb += gridDim.x) {
+        __syncthreads();
+        const VBlk t = tab[vb];
+        const Inst &I = insts[t.inst];
+        if (inst_active(I))
+            reduce_fused_body<CPM>(I, t.blk);
     }
 }
 
@@ -404,38 +485,32 @@ __device__ __forceinline__ void team_slot_sum(TA (&acc)[NE]) {
 // after the light rows, and k_spmm_combine adds the chunk sums of each heavy
 // row in chunk order.
 template <typename TU, typename TZ, typename TX, typename VS, int CP>
-__global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ row_ptr,
-                                              const int32_t *__restrict__ col,
-                                              const VS *__restrict__ val,
-                                              const TU *const *__restrict__ Uring,
-                                              const TX *const *__restrict__ Xring,
-                                              TZ *const *__restrict__ Zring, int64_t n,
-                                              int diag_unit, double *__restrict__ trace_part,
-                                              const DevState *__restrict__ st, int role,
-                                              int64_t heavy_thr,
-                                              const int32_t *__restrict__ chunk_row,
-                                              const int64_t *__restrict__ chunk_beg,
-                                              const int32_t *__restrict__ chunk_len,
-                                              int64_t nchunks,
-                                              typename AccumOf<TU>::type *__restrict__ chunk_sum) {
+__device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, int64_t nblk) {
     using Cfg = SpmmCfg<TU, CP>;
     using TA = typename AccumOf<TU>::type;
     constexpr int NE = Cfg::LANE_ELEMS;
     constexpr int DEPTH = 4;
-    if (st && !st->active)
-        return;
-    const int slot_role = st ? st->role[role] : 0;
-    const TX *__restrict__ X = Xring[slot_role];
-    TZ *__restrict__ Z = Zring[slot_role];
-    const TU *__restrict__ U = Uring[slot_role];
+    const int slot_role = ring_slot(I, role);
+    const TX *__restrict__ X = (const TX *)I.X[slot_role];
+    TZ *__restrict__ Z = (TZ *)I.Z[slot_role];
+    const TU *__restrict__ U =
+        sizeof(TU) == 2 ? (const TU *)I.Sh[slot_role] : (const TU *)I.X[slot_role];
+    const int64_t *__restrict__ row_ptr = I.row_ptr;
+    const int32_t *__restrict__ col = I.col;
+    const VS *__restrict__ val = (const VS *)I.val;
+    const int64_t n = I.n, heavy_thr = I.heavy_thr, nchunks = I.nchunks;
+    const int diag_unit = I.diag_unit;
+    const int64_t *__restrict__ chunk_beg = I.chunk_beg;
+    const int32_t *__restrict__ chunk_len = I.chunk_len;
+    TA *__restrict__ chunk_sum = (TA *)I.chunk_sum;
 
     const int tid = threadIdx.x;
     const int team = tid / Cfg::TEAM, lt = tid % Cfg::TEAM;
     const int slot = lt / Cfg::GS, sub = lt % Cfg::GS;
     double trace_acc = 0.0;
     const int64_t nblocks = (n + Cfg::ROWS_PER_WG - 1) / Cfg::ROWS_PER_WG;
-    for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
-        const int64_t row = blk * Cfg::ROWS_PER_WG + team;
+    for (int64_t rb = blk; rb < nblocks; rb += nblk) {
+        const int64_t row = rb * Cfg::ROWS_PER_WG + team;
         TA acc[NE];
 #pragma unroll
         for (int q = 0; q < NE; ++q)
@@ -473,7 +548,7 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ row_pt
     }
     // chunks of heavy rows
     constexpr int TEAMS = 256 / Cfg::TEAM;
-    for (int64_t k = (int64_t)blockIdx.x * TEAMS + team; k < nchunks; k += (int64_t)gridDim.x * TEAMS) {
+    for (int64_t k = blk * TEAMS + team; k < nchunks; k += nblk * TEAMS) {
         TA acc[NE];
 #pragma unroll
         for (int q = 0; q < NE; ++q)
@@ -485,7 +560,6 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ row_pt
 #pragma unroll
             for (int q = 0; q < NE; ++q)
                 chunk_sum[k * CP + sub * NE + q] = acc[q];
-        (void)chunk_row;
     }
     __shared__ double sh[256];
     sh[tid] = trace_acc;
@@ -496,31 +570,46 @@ __global__ __launch_bounds__(256) void k_spmm(const int64_t *__restrict__ row_pt
         __syncthreads();
     }
     if (tid == 0)
-        trace_part[blockIdx.x] = sh[0];
+        I.part_spmm[blk] = sh[0];
+    __syncthreads();
+}
+
+template <typename TU, typename TZ, typename TX, typename VS, int CP>
+__global__ __launch_bounds__(256) void k_spmm_1(Inst I, int role) {
+    if (inst_active(I))
+        spmm_body<TU, TZ, TX, VS, CP>(I, role, blockIdx.x, gridDim.x);
+}
+template <typename TU, typename TZ, typename TX, typename VS, int CP>
+__global__ __launch_bounds__(256) void k_spmm_b(const Inst *__restrict__ insts,
+                                                const VBlk *__restrict__ tab,
+                                                const int32_t *__restrict__ count, int role) {
+    for (int64_t vb = blockIdx.x; vb < *count; vb += gridDim.x) {
+        __syncthreads();
+        const VBlk t = tab[vb];
+        const Inst &I = insts[t.inst];
+        if (inst_active(I))
+            spmm_body<TU, TZ, TX, VS, CP>(I, role, t.blk, I.g_spmm);
+    }
 }
 
 // Heavy rows: z_i = sum of the row's chunk sums in chunk order (+ u_i for the
 // unit diagonal), and the terms <u_i, z_i>.  One thread per component of a
 // row, 256/CP rows per workgroup step; partials go to trace_part[blockIdx].
 template <typename TA, typename TZ, typename TX, int CP>
-__global__ __launch_bounds__(256) void k_spmm_combine(const int32_t *__restrict__ heavy_rows,
-                                                      const int32_t *__restrict__ heavy_chunk_ptr,
-                                                      int64_t nheavy,
-                                                      const TA *__restrict__ chunk_sum,
-                                                      const TX *const *__restrict__ Xring,
-                                                      TZ *const *__restrict__ Zring, int diag_unit,
-                                                      double *__restrict__ trace_part,
-                                                      const DevState *__restrict__ st, int role) {
+__device__ __forceinline__ void combine_body(const Inst &I, int role, int64_t blk, int64_t nblk) {
     constexpr int RPB = 256 / CP;
-    if (st && !st->active)
-        return;
-    const int slot_role = st ? st->role[role] : 0;
-    const TX *__restrict__ X = Xring[slot_role];
-    TZ *__restrict__ Z = Zring[slot_role];
+    const int slot_role = ring_slot(I, role);
+    const TX *__restrict__ X = (const TX *)I.X[slot_role];
+    TZ *__restrict__ Z = (TZ *)I.Z[slot_role];
+    const int32_t *__restrict__ heavy_rows = I.heavy_rows;
+    const int32_t *__restrict__ heavy_chunk_ptr = I.heavy_chunk_ptr;
+    const TA *__restrict__ chunk_sum = (const TA *)I.chunk_sum;
+    const int64_t nheavy = I.nheavy;
+    const int diag_unit = I.diag_unit;
     const int tid = threadIdx.x, k = tid % CP, rl = tid / CP;
     __shared__ double sh[256];
     double trace_acc = 0.0;
-    for (int64_t h0 = (int64_t)blockIdx.x * RPB; h0 < nheavy; h0 += (int64_t)gridDim.x * RPB) {
+    for (int64_t h0 = blk * RPB; h0 < nheavy; h0 += nblk * RPB) {
         const int64_t h = h0 + rl;
         if (h < nheavy) {
             const int64_t row = heavy_rows[h];
@@ -542,7 +631,26 @@ __global__ __launch_bounds__(256) void k_spmm_combine(const int32_t *__restrict_
         __syncthreads();
     }
     if (tid == 0)
-        trace_part[blockIdx.x] = sh[0];
+        I.part_spmm[I.g_spmm + blk] = sh[0];
+    __syncthreads();
+}
+
+template <typename TA, typename TZ, typename TX, int CP>
+__global__ __launch_bounds__(256) void k_combine_1(Inst I, int role) {
+    if (inst_active(I))
+        combine_body<TA, TZ, TX, CP>(I, role, blockIdx.x, gridDim.x);
+}
+template <typename TA, typename TZ, typename TX, int CP>
+__global__ __launch_bounds__(256) void k_combine_b(const Inst *__restrict__ insts,
+                                                   const VBlk *__restrict__ tab,
+                                                   const int32_t *__restrict__ count, int role) {
+    for (int64_t vb = blockIdx.x; vb < *count; vb += gridDim.x) {
+        __syncthreads();
+        const VBlk t = tab[vb];
+        const Inst &I = insts[t.inst];
+        if (inst_active(I))
+            combine_body<TA, TZ, TX, CP>(I, role, t.blk, I.g_comb);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -682,12 +790,7 @@ __device__ __forceinline__ double simplex_threshold(const T (&v)[NC], const bool
 // the 16 x 16 blocks of their Gram matrices on the matrix cores.
 // ---------------------------------------------------------------------------
 template <typename T, int CP, bool ACCEL, bool BT, bool SHADOW>
-__global__ __launch_bounds__(256) void k_fused(T *const *__restrict__ Xring,
-                                               T *const *__restrict__ Zring,
-                                               __hip_bfloat16 *const *__restrict__ shadow_ring,
-                                               const T *__restrict__ GYs, int64_t n, int c,
-                                               double *__restrict__ part,
-                                               const DevState *__restrict__ st) {
+__device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t nblk) {
     constexpr int CPM = CP < 16 ? 16 : CP;
     constexpr int M = CPM / 16;
     constexpr int NC = 4 * M;
@@ -701,8 +804,13 @@ __global__ __launch_bounds__(256) void k_fused(T *const *__restrict__ Xring,
     using A4 = typename Acc4<T>::type;
     using L = FusedLayout<CPM>;
 
-    if (!st->active)
-        return;
+    const DevState *__restrict__ st = I.st;
+    T *const *Xring = (T *const *)I.X;
+    T *const *Zring = (T *const *)I.Z;
+    __hip_bfloat16 *const *shadow_ring = (__hip_bfloat16 *const *)I.Sh;
+    const T *__restrict__ GYs = (const T *)I.GYs;
+    const int64_t n = I.n;
+    const int c = I.c;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r = lane & 15, g = lane >> 4;
     const T *__restrict__ Xc = Xring[st->role[ROLE_C]];
@@ -735,7 +843,7 @@ __global__ __launch_bounds__(256) void k_fused(T *const *__restrict__ Xring,
         acc64[k] = doublex4{0, 0, 0, 0};
 
     const int64_t nwt = (n + 63) / 64;
-    for (int64_t wt = blockIdx.x; wt < nwt; wt += gridDim.x) {
+    for (int64_t wt = blk; wt < nwt; wt += nblk) {
         const int64_t row = wt * 64 + wave * 16 + r;
         const bool live = row < n;
         T xc[NC], xp[NC], zc[NC], zp[NC];
@@ -887,7 +995,7 @@ __global__ __launch_bounds__(256) void k_fused(T *const *__restrict__ Xring,
     }
 
     // write this workgroup's partials
-    double *out = part + (int64_t)blockIdx.x * L::NE;
+    double *out = I.part_fused + blk * L::NE;
 #pragma unroll
     for (int kk = 0; kk < BPW; ++kk) {
         const int kb = wave + 4 * kk;
@@ -937,6 +1045,25 @@ __global__ __launch_bounds__(256) void k_fused(T *const *__restrict__ Xring,
             s = ((shs[0][tid] + shs[1][tid]) + shs[2][tid]) + shs[3][tid];
         out[3 * L::MAT + tid] = s;
     }
+    __syncthreads();
+}
+
+template <typename T, int CP, bool ACCEL, bool BT, bool SHADOW>
+__global__ __launch_bounds__(256) void k_fused_1(Inst I) {
+    if (inst_active(I))
+        fused_body<T, CP, ACCEL, BT, SHADOW>(I, blockIdx.x, gridDim.x);
+}
+template <typename T, int CP, bool ACCEL, bool BT, bool SHADOW>
+__global__ __launch_bounds__(256) void k_fused_b(const Inst *__restrict__ insts,
+                                                 const VBlk *__restrict__ tab,
+                                                 const int32_t *__restrict__ count) {
+    for (int64_t vb = blockIdx.x; vb < *count; vb += gridDim.x) {
+        __syncthreads();
+        const VBlk t = tab[vb];
+        const Inst &I = insts[t.inst];
+        if (inst_active(I))
+            fused_body<T, CP, ACCEL, BT, SHADOW>(I, t.blk, I.g_fused);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -946,22 +1073,39 @@ __global__ __launch_bounds__(256) void k_fused(T *const *__restrict__ Xring,
 // mode 1: after the fused kernel and the product of the trial point.
 // ---------------------------------------------------------------------------
 template <typename T, int CPM>
-__global__ __launch_bounds__(256) void k_control(DevState *__restrict__ st, int mode,
-                                                 const double *__restrict__ red_mats,
-                                                 const double *__restrict__ red_trace,
-                                                 double *__restrict__ GY64,
-                                                 T *__restrict__ GYs,
-                                                 const double *__restrict__ sched,
-                                                 double *__restrict__ hist_f,
-                                                 double *__restrict__ hist_tau,
-                                                 int32_t *__restrict__ hist_trials,
-                                                 double *__restrict__ hist_r) {
+__device__ __forceinline__ void control_body(const Inst &I, int mode) {
     using L = FusedLayout<CPM>;
     __shared__ double sh[256];
     __shared__ int decision;
+    DevState *__restrict__ st = I.st;
+    const double *__restrict__ red_mats = I.red_mats;
+    double *__restrict__ GY64 = I.GY64;
+    T *__restrict__ GYs = (T *)I.GYs;
+    const double *__restrict__ sched = I.sched;
+    double *__restrict__ hist_f = I.hist_f;
+    double *__restrict__ hist_tau = I.hist_tau;
+    int32_t *__restrict__ hist_trials = I.hist_trials;
+    double *__restrict__ hist_r = I.hist_r;
     const int tid = threadIdx.x;
     if (mode == 1 && !st->active)
         return;
+    // the products' terms sum_i <x_i, (S X)_i>: workgroup partials of the
+    // sparse product, combined in a fixed order
+    {
+        const int64_t np = (int64_t)I.g_spmm + I.g_comb;
+        double a = 0.0;
+        for (int64_t q = tid; q < np; q += 256)
+            a += I.part_spmm[q];
+        sh[tid] = a;
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if (tid < s)
+                sh[tid] += sh[tid + s];
+            __syncthreads();
+        }
+    }
+    const double tr_total = sh[0];
+    __syncthreads();
     const int c = st->c;
     const double *Gp = red_mats;                       // Gram of the new point
     const double *Gnext = red_mats + (mode == 1 && st->accelerate ? L::MAT : 0);
@@ -995,7 +1139,7 @@ __global__ __launch_bounds__(256) void k_control(DevState *__restrict__ st, int 
     __syncthreads();
 
     if (tid == 0) {
-        const double tr_p = red_trace[0];
+        const double tr_p = tr_total;
         const double f_p = st->s2 + gp_sq - 2.0 * tr_p;
         int accept = 1;
         if (mode == 0) {
@@ -1126,6 +1270,20 @@ __global__ __launch_bounds__(256) void k_control(DevState *__restrict__ st, int 
     }
     if (tid == 0)
         st->mu = mu;
+    __syncthreads();
+}
+
+template <typename T, int CPM> __global__ __launch_bounds__(256) void k_control_1(Inst I, int mode) {
+    control_body<T, CPM>(I, mode);
+}
+template <typename T, int CPM>
+__global__ __launch_bounds__(256) void k_control_b(const Inst *__restrict__ insts,
+                                                   const VBlk *__restrict__ tab,
+                                                   const int32_t *__restrict__ count) {
+    for (int64_t vb = blockIdx.x; vb < *count; vb += gridDim.x) {
+        __syncthreads();
+        control_body<T, CPM>(insts[tab[vb].inst], 1);
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -173,27 +173,35 @@ fc_status build_heavy_plan(const int64_t *d_row_ptr, int64_t n, size_t acc_bytes
     return FC_OK;
 }
 
-int combine_grid(int64_t nheavy, int cp) {
+int combine_grid(int64_t nheavy, int rows_per_block) {
     if (nheavy == 0)
         return 0;
-    return grid_1d(nheavy, 256 / cp, 1024);
+    return grid_1d(nheavy, rows_per_block, 1024);
 }
 
-// Sparse product of the ring slot `role` (or slot 0 without a state) with
-// the heavy-row plan, writing g_spmm + g_comb trace partials.
+// Copy the heavy-row plan into an instance descriptor.
+void plan_to_inst(const HeavyPlan &hp, Inst &I) {
+    I.heavy_thr = hp.nheavy > 0 ? HEAVY_THR : INT64_MAX;
+    I.nchunks = hp.nchunks;
+    I.nheavy = hp.nheavy;
+    I.chunk_row = hp.chunk_row;
+    I.chunk_beg = hp.chunk_beg;
+    I.chunk_len = hp.chunk_len;
+    I.heavy_rows = hp.rows;
+    I.heavy_chunk_ptr = hp.chunk_ptr;
+    I.chunk_sum = hp.chunk_sum;
+    I.g_comb = combine_grid(hp.nheavy, 1);
+}
+
+// Sparse product of ring slot `role` of one instance: light rows and chunks,
+// then the per-row combination of the chunks (writes g_spmm + g_comb trace
+// partials).
 template <typename TU, typename TZ, typename TX, typename VS, int CP>
-void launch_spmm(const int64_t *row_ptr, const int32_t *col, const VS *val, const TU *const *Ur,
-                 const TX *const *Xr, TZ *const *Zr, int64_t n, int diag_unit, double *trace_part,
-                 int g_spmm, const DevState *st, int role, const HeavyPlan &hp, hipStream_t s) {
+void launch_spmm(const Inst &I, int role, hipStream_t s) {
     using TA = typename AccumOf<TU>::type;
-    hipLaunchKernelGGL((k_spmm<TU, TZ, TX, VS, CP>), dim3(g_spmm), dim3(256), 0, s, row_ptr, col, val,
-                       Ur, Xr, Zr, n, diag_unit, trace_part, st, role,
-                       hp.nheavy > 0 ? HEAVY_THR : INT64_MAX, hp.chunk_row, hp.chunk_beg,
-                       hp.chunk_len, hp.nchunks, (TA *)hp.chunk_sum);
-    if (hp.nheavy > 0)
-        hipLaunchKernelGGL((k_spmm_combine<TA, TZ, TX, CP>), dim3(combine_grid(hp.nheavy, CP)),
-                           dim3(256), 0, s, hp.rows, hp.chunk_ptr, hp.nheavy, (const TA *)hp.chunk_sum,
-                           Xr, Zr, diag_unit, trace_part + g_spmm, st, role);
+    hipLaunchKernelGGL((k_spmm_1<TU, TZ, TX, VS, CP>), dim3(I.g_spmm), dim3(256), 0, s, I, role);
+    if (I.nheavy > 0)
+        hipLaunchKernelGGL((k_combine_1<TA, TZ, TX, CP>), dim3(I.g_comb), dim3(256), 0, s, I, role);
 }
 
 // Dispatch a functor on the padded width CP in {4, 8, 16, 32, 64}.
@@ -335,15 +343,15 @@ struct fc_solver {
     void *X[3] = {nullptr, nullptr, nullptr};
     void *Z[3] = {nullptr, nullptr, nullptr};
     void *shadow[3] = {nullptr, nullptr, nullptr};
-    void **d_Xring = nullptr, **d_Zring = nullptr, **d_Sring = nullptr;
     DevState *d_state = nullptr;
     DevState h = {};
     double *d_GY64 = nullptr;
     void *d_GYs = nullptr;
     double *d_part_fused = nullptr, *d_part_spmm = nullptr, *d_part_gram = nullptr;
-    int g_fused = 1, g_spmm = 1, g_gram = 1, g_comb = 0;
+    int g_fused = 1, g_spmm = 1, g_gram = 1, g_comb = 0, g_red = 1;
     HeavyPlan heavy;
-    double *d_red_mats = nullptr, *d_red_trace = nullptr;
+    Inst inst = {};
+    double *d_red_mats = nullptr;
     double *d_sched = nullptr;
     int sched_len = 0;
     double *d_hist_f = nullptr, *d_hist_tau = nullptr, *d_hist_r = nullptr;
@@ -378,18 +386,13 @@ int fused_ne(int cpm) { return 3 * cpm * cpm + FUSED_NSCAL; }
 template <typename T, typename TU, typename VS, int CP>
 fc_status launch_trial_t(fc_solver *h, hipEvent_t *ev) {
     constexpr int CPM = CP < 16 ? 16 : CP;
-    using Cfg = SpmmCfg<TU, CP>;
     hipStream_t s = h->stream;
     const bool shadow = h->prec == FC_PREC_MIXED;
-    auto Xr = (T *const *)h->d_Xring;
-    auto Zr = (T *const *)h->d_Zring;
-    auto Sr = (__hip_bfloat16 *const *)h->d_Sring;
-    auto GYs = (const T *)h->d_GYs;
+    const Inst &I = h->inst;
     if (ev)
         HIPCHK(hipEventRecord(ev[0], s));
-#define FUSED_LAUNCH(A, B, SH)                                                                 \
-    hipLaunchKernelGGL((k_fused<T, CP, A, B, SH>), dim3(h->g_fused), dim3(256), 0, s, Xr, Zr, Sr, \
-                       GYs, h->n, h->c, h->d_part_fused, (const DevState *)h->d_state)
+#define FUSED_LAUNCH(A, B, SH) \
+    hipLaunchKernelGGL((k_fused_1<T, CP, A, B, SH>), dim3(h->g_fused), dim3(256), 0, s, I)
     if constexpr (std::is_same<T, float>::value) {
         if (shadow) {
             if (h->accelerate && h->backtrack) FUSED_LAUNCH(true, true, true);
@@ -411,25 +414,15 @@ fc_status launch_trial_t(fc_solver *h, hipEvent_t *ev) {
 #undef FUSED_LAUNCH
     if (ev)
         HIPCHK(hipEventRecord(ev[1], s));
-    const TU *const *Ur = shadow ? (const TU *const *)h->d_Sring : (const TU *const *)h->d_Xring;
-    launch_spmm<TU, T, T, VS, CP>(h->row_ptr, h->col, (const VS *)h->val, Ur,
-                                  (const T *const *)h->d_Xring, Zr, h->n,
-                                  (int)(h->diag == FC_DIAG_UNIT), h->d_part_spmm, h->g_spmm,
-                                  (const DevState *)h->d_state, (int)ROLE_N, h->heavy, s);
+    launch_spmm<TU, T, T, VS, CP>(I, (int)ROLE_N, s);
     if (ev)
         HIPCHK(hipEventRecord(ev[2], s));
-    const int ne = fused_ne(CPM);
-    launch_reduce(h->d_part_fused, h->g_fused, ne, ne, h->d_red_mats, s);
-    launch_reduce(h->d_part_spmm, h->g_spmm + h->g_comb, 1, 1, h->d_red_trace, s);
+    hipLaunchKernelGGL((k_reduce_fused_1<CPM>), dim3(h->g_red), dim3(256), 0, s, I);
     if (ev)
         HIPCHK(hipEventRecord(ev[3], s));
-    hipLaunchKernelGGL((k_control<T, CPM>), dim3(1), dim3(256), 0, s, h->d_state, 1,
-                       (const double *)h->d_red_mats, (const double *)h->d_red_trace, h->d_GY64,
-                       (T *)h->d_GYs, (const double *)h->d_sched, h->d_hist_f, h->d_hist_tau,
-                       h->d_hist_trials, h->d_hist_r);
+    hipLaunchKernelGGL((k_control_1<T, CPM>), dim3(1), dim3(256), 0, s, I, 1);
     if (ev)
         HIPCHK(hipEventRecord(ev[4], s));
-    (void)Cfg::TEAM;
     HIPCHK(hipGetLastError());
     return FC_OK;
 }
@@ -447,17 +440,9 @@ fc_status launch_init_t(fc_solver *h) {
         hipLaunchKernelGGL((k_convert<float, __hip_bfloat16>), dim3(grid_1d(h->n * h->cp, 256, 8192)),
                            dim3(256), 0, s, (const float *)h->X[0], (__hip_bfloat16 *)h->shadow[0],
                            h->n * h->cp);
-    const TU *const *Ur = shadow ? (const TU *const *)h->d_Sring : (const TU *const *)h->d_Xring;
-    launch_spmm<TU, T, T, VS, CP>(h->row_ptr, h->col, (const VS *)h->val, Ur,
-                                  (const T *const *)h->d_Xring, (T *const *)h->d_Zring, h->n,
-                                  (int)(h->diag == FC_DIAG_UNIT), h->d_part_spmm, h->g_spmm,
-                                  (const DevState *)h->d_state, (int)ROLE_C, h->heavy, s);
     launch_reduce(h->d_part_gram, (int64_t)h->g_gram * 4, ld, ld, h->d_red_mats, s);
-    launch_reduce(h->d_part_spmm, h->g_spmm + h->g_comb, 1, 1, h->d_red_trace, s);
-    hipLaunchKernelGGL((k_control<T, CPM>), dim3(1), dim3(256), 0, s, h->d_state, 0,
-                       (const double *)h->d_red_mats, (const double *)h->d_red_trace, h->d_GY64,
-                       (T *)h->d_GYs, (const double *)h->d_sched, h->d_hist_f, h->d_hist_tau,
-                       h->d_hist_trials, h->d_hist_r);
+    launch_spmm<TU, T, T, VS, CP>(h->inst, (int)ROLE_C, s);
+    hipLaunchKernelGGL((k_control_1<T, CPM>), dim3(1), dim3(256), 0, s, h->inst, 0);
     HIPCHK(hipGetLastError());
     return FC_OK;
 }
@@ -741,17 +726,10 @@ fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_d
         h->val = h->val_owned;
         h->vdt = FC_F16;
     }
-    if (h->alloc(&h->d_Xring, 3 * sizeof(void *)) != hipSuccess ||
-        h->alloc(&h->d_Zring, 3 * sizeof(void *)) != hipSuccess ||
-        h->alloc(&h->d_Sring, 3 * sizeof(void *)) != hipSuccess ||
-        h->alloc(&h->d_state, sizeof(DevState)) != hipSuccess ||
+    if (h->alloc(&h->d_state, sizeof(DevState)) != hipSuccess ||
         h->alloc(&h->d_GY64, sizeof(double) * h->cpm * h->cpm) != hipSuccess ||
         h->alloc(&h->d_GYs, esz * h->cpm * h->cpm) != hipSuccess)
         return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "solver state"));
-    if (hipMemcpyAsync(h->d_Xring, h->X, sizeof(h->X), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(h->d_Zring, h->Z, sizeof(h->Z), hipMemcpyHostToDevice, s) != hipSuccess ||
-        hipMemcpyAsync(h->d_Sring, h->shadow, sizeof(h->shadow), hipMemcpyHostToDevice, s) != hipSuccess)
-        return cleanup(fail(FC_ERR_DEVICE, "pointer tables"));
 
     // launch geometry: persistent grids sized to the device
     const int cus = device_cus();
@@ -774,18 +752,48 @@ fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_d
     st = build_heavy_plan(S->row_ptr, S->n, h->prec == FC_PREC_FP64 ? 8 : 4, h->cp, s, h->heavy);
     if (st != FC_OK)
         return cleanup(st);
-    h->g_comb = combine_grid(h->heavy.nheavy, h->cp);
+    h->g_comb = combine_grid(h->heavy.nheavy, 256 / h->cp);
+    h->g_red = (int)cdiv(fused_ne(h->cpm), 64);
     const int ne = fused_ne(h->cpm);
     if (h->alloc(&h->d_part_fused, sizeof(double) * (size_t)h->g_fused * ne) != hipSuccess ||
         h->alloc(&h->d_part_spmm, sizeof(double) * (size_t)(h->g_spmm + h->g_comb)) != hipSuccess ||
         h->alloc(&h->d_part_gram, sizeof(double) * (size_t)h->g_gram * 4 * h->cpm * h->cpm) != hipSuccess ||
         h->alloc(&h->d_red_mats, sizeof(double) * ne) != hipSuccess ||
-        h->alloc(&h->d_red_trace, sizeof(double) * 2) != hipSuccess ||
         h->alloc(&h->d_hist_f, sizeof(double) * h->hist_cap) != hipSuccess ||
         h->alloc(&h->d_hist_tau, sizeof(double) * h->hist_cap) != hipSuccess ||
         h->alloc(&h->d_hist_r, sizeof(double) * h->hist_cap) != hipSuccess ||
         h->alloc(&h->d_hist_trials, sizeof(int32_t) * h->hist_cap) != hipSuccess)
         return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "partial-sum buffers"));
+    {
+        Inst &I = h->inst;
+        I.row_ptr = h->row_ptr;
+        I.col = h->col;
+        I.val = h->val;
+        I.n = h->n;
+        I.c = h->c;
+        I.diag_unit = h->diag == FC_DIAG_UNIT ? 1 : 0;
+        plan_to_inst(h->heavy, I);
+        for (int k = 0; k < 3; ++k) {
+            I.X[k] = h->X[k];
+            I.Z[k] = h->Z[k];
+            I.Sh[k] = h->shadow[k];
+        }
+        I.st = h->d_state;
+        I.GY64 = h->d_GY64;
+        I.GYs = h->d_GYs;
+        I.part_fused = h->d_part_fused;
+        I.part_spmm = h->d_part_spmm;
+        I.red_mats = h->d_red_mats;
+        I.g_fused = h->g_fused;
+        I.g_spmm = h->g_spmm;
+        I.g_comb = h->g_comb;
+        I.g_red = h->g_red;
+        I.hist_f = h->d_hist_f;
+        I.hist_tau = h->d_hist_tau;
+        I.hist_r = h->d_hist_r;
+        I.hist_trials = h->d_hist_trials;
+        I.sched = nullptr;
+    }
     if (hipMemsetAsync(h->d_red_mats, 0, sizeof(double) * ne, s) != hipSuccess ||
         hipMemsetAsync(h->d_hist_trials, 0, sizeof(int32_t) * h->hist_cap, s) != hipSuccess)
         return cleanup(fail(FC_ERR_DEVICE, "memset"));
@@ -799,6 +807,7 @@ fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_d
         for (int k = 0; k < h->sched_len; ++k)
             if (!(opt->step_schedule[k] > 0.0))
                 return cleanup(fail(FC_ERR_INVALID_ARG, "step schedule entries must be > 0"));
+        h->inst.sched = h->d_sched;
     }
 
     // Xbar_0 (the other two ring slots start as copies of it)
@@ -1151,24 +1160,28 @@ fc_status spmm_and_gram_t(const fc_csr *S, fc_diag diag, const T *Upad, T *Zpad,
     using Cfg = SpmmCfg<T, CP>;
     const int64_t n = S->n;
     const int cus = device_cus();
-    const int g_spmm = grid_1d(n, Cfg::ROWS_PER_WG, (int64_t)cus * 32);
-    DevBuf ring, part, red;
-    HIPCHK(dev_alloc(ring, 2 * sizeof(void *), s));
-    const void *ptrs[2] = {Upad, Zpad};
-    HIPCHK(hipMemcpyAsync(ring.p, ptrs, sizeof(ptrs), hipMemcpyHostToDevice, s));
-    const T *const *Ur = (const T *const *)ring.p;
-    T *const *Zr = (T *const *)((void **)ring.p + 1);
     HeavyPlan hp;
     fc_status st = build_heavy_plan(S->row_ptr, n, sizeof(T), CP, s, hp);
     if (st != FC_OK)
         return st;
-    const int g_comb = combine_grid(hp.nheavy, CP);
-    HIPCHK(dev_alloc(part, sizeof(double) * (g_spmm + g_comb), s));
+    Inst I = {};
+    I.row_ptr = S->row_ptr;
+    I.col = S->col_idx;
+    I.val = S->values;
+    I.n = n;
+    I.c = CP;
+    I.diag_unit = diag == FC_DIAG_UNIT ? 1 : 0;
+    plan_to_inst(hp, I);
+    I.g_spmm = grid_1d(n, Cfg::ROWS_PER_WG, (int64_t)cus * 32);
+    I.g_comb = combine_grid(hp.nheavy, 256 / CP);
+    I.X[0] = (void *)Upad;
+    I.Z[0] = Zpad;
+    DevBuf part, red;
+    HIPCHK(dev_alloc(part, sizeof(double) * (I.g_spmm + I.g_comb), s));
     HIPCHK(dev_alloc(red, sizeof(double) * (1 + CPM * CPM), s));
-    launch_spmm<T, T, T, VS, CP>(S->row_ptr, S->col_idx, (const VS *)S->values, Ur, Ur, Zr, n,
-                                 (int)(diag == FC_DIAG_UNIT), (double *)part.p, g_spmm,
-                                 (const DevState *)nullptr, 0, hp, s);
-    launch_reduce((const double *)part.p, g_spmm + g_comb, 1, 1, (double *)red.p, s);
+    I.part_spmm = (double *)part.p;
+    launch_spmm<T, T, T, VS, CP>(I, 0, s);
+    launch_reduce((const double *)part.p, I.g_spmm + I.g_comb, 1, 1, (double *)red.p, s);
     DevBuf gpart;
     if (want_gram) {
         const int g_gram = grid_1d(cdiv(n, 16), 4, (int64_t)cus * 2);
