@@ -114,7 +114,9 @@ typedef struct {
     double tol_pgrad;          /* stop when r_n <= tol_pgrad * r_1, with
                                   r_n = ||Y_n - Xbar_n||_F / tau_n; 0 disables */
     int32_t validate;          /* 1: check CSR structure and symmetry at fc_create */
-    int32_t reserved0;
+    int32_t norm_estimate;     /* ||S||_2 in L_thm: 0 = power iteration (default);
+                                  1 = the Frobenius norm ||S||_F, an upper bound, as the
+                                  paper's experiments do (section 5, hyperparameters) */
     const double *step_schedule; /* host: tau_n for n = 1..step_schedule_len, copied at
                                     fc_create; used by FC_STEP_FIXED when non-NULL */
     int32_t step_schedule_len;

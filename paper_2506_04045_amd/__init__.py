@@ -95,7 +95,7 @@ class Solver:
                  backtrack: bool = False, L0: float = 0.0, eta: float = 2.0,
                  max_iter: int = 100, check_every: int = 16, tol_loss: float = math.nan,
                  tol_pgrad: float = 0.0, validate: bool = False, step_schedule=None,
-                 stream=None):
+                 norm_estimate: str = "power", stream=None):
         lib = N.load()
         self._csr = _CsrView(row_ptr, col_idx, val)
         self.n, self.c = self._csr.n, int(c)
@@ -114,6 +114,7 @@ class Solver:
         opt.tol_loss = float(tol_loss)
         opt.tol_pgrad = float(tol_pgrad)
         opt.validate = int(bool(validate))
+        opt.norm_estimate = {"power": 0, "frobenius": 1}[norm_estimate]
         self._sched = None
         if step_schedule is not None:
             self._sched = np.ascontiguousarray(step_schedule, dtype=np.float64)

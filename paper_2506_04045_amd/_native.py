@@ -45,7 +45,7 @@ class Options(ctypes.Structure):
                 ("step", ctypes.c_double), ("L0", ctypes.c_double), ("eta", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32),
                 ("tol_loss", ctypes.c_double), ("tol_pgrad", ctypes.c_double),
-                ("validate", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+                ("validate", ctypes.c_int32), ("norm_estimate", ctypes.c_int32),
                 ("step_schedule", ctypes.POINTER(ctypes.c_double)),
                 ("step_schedule_len", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 

@@ -361,16 +361,24 @@ struct fc_solver {
     int max_iter = 100;
     double spec_norm = 0.0, L_thm = 0.0;
     std::vector<void *> allocs;
+    bool pooled = false;  // stream-ordered allocations (serving instances)
+    size_t bytes_held = 0;
 
     ~fc_solver() {
-        for (void *p : allocs)
-            (void)hipFree(p);
+        for (void *p : allocs) {
+            if (pooled)
+                (void)hipFreeAsync(p, stream);
+            else
+                (void)hipFree(p);
+        }
     }
     template <typename P> hipError_t alloc(P **p, size_t bytes) {
         void *q = nullptr;
-        hipError_t e = hipMalloc(&q, bytes > 0 ? bytes : 16);
+        const size_t b = bytes > 0 ? bytes : 16;
+        hipError_t e = pooled ? hipMallocAsync(&q, b, stream) : hipMalloc(&q, b);
         if (e == hipSuccess) {
             allocs.push_back(q);
+            bytes_held += b;
             *p = (P *)q;
         }
         return e;
@@ -613,9 +621,14 @@ void fc_options_default(fc_options *opt) {
 
 const char *fc_last_error(void) { return g_last_error.c_str(); }
 
-fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_dtype u0_dtype,
-                    void *stream, fc_solver **out) {
-    g_last_error.clear();
+}  // extern "C"
+
+namespace {
+
+// Set-up shared by fc_create and the serving engine: `hist_cap` iterations
+// of history, allocations from the stream-ordered pool when `pooled`.
+fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc_dtype u0_dtype,
+                      hipStream_t stream, int hist_cap, bool pooled, fc_solver **out) {
     if (!out)
         return fail(FC_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
@@ -639,6 +652,8 @@ fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_d
         return fail(FC_ERR_INVALID_ARG, "max_iter < 0");
     if (opt->step_schedule && opt->step_schedule_len < 1)
         return fail(FC_ERR_INVALID_ARG, "step_schedule_len must be >= 1");
+    if (opt->norm_estimate != 0 && opt->norm_estimate != 1)
+        return fail(FC_ERR_INVALID_ARG, "norm_estimate must be 0 or 1");
     if (U0 && u0_dtype != FC_F64 && u0_dtype != FC_F32)
         return fail(FC_ERR_INVALID_ARG, "U0 must be FC_F64 or FC_F32");
     if (opt->precision == FC_PREC_FP64 && S->values_dtype != FC_F64)
@@ -670,16 +685,17 @@ fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_d
     h->col = S->col_idx;
     h->val = S->values;
     h->vdt = S->values_dtype;
-    h->stream = (hipStream_t)stream;
+    h->stream = stream;
+    h->pooled = pooled;
+    h->hist_cap = hist_cap;
     h->check_every = opt->check_every > 0 ? opt->check_every : 16;
     h->max_iter = opt->max_iter;
     hipStream_t s = h->stream;
 
     if (opt->validate) {
         int32_t *flags = nullptr;
-        if (hipMalloc(&flags, sizeof(int32_t)) != hipSuccess)
+        if (h->alloc(&flags, sizeof(int32_t)) != hipSuccess)
             return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "validation buffer"));
-        h->allocs.push_back(flags);
         if (hipMemsetAsync(flags, 0, sizeof(int32_t), s) != hipSuccess)
             return cleanup(fail(FC_ERR_DEVICE, "memset"));
         const int g = grid_1d(S->n, 256, 8192);
@@ -847,10 +863,14 @@ fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_d
     const bool need_L = (!h->backtrack && !(opt->step > 0.0) && !opt->step_schedule) ||
                         (h->backtrack && !(opt->L0 > 0.0));
     if (need_L) {
-        int32_t its = 0;
-        st = power_norm(&Sv, (int)(h->diag == FC_DIAG_UNIT), 1000, 1e-12, s, &h->spec_norm, &its);
-        if (st != FC_OK)
-            return cleanup(st);
+        if (opt->norm_estimate == 1) {
+            h->spec_norm = std::sqrt(s2);   // ||S_eff||_F >= ||S_eff||_2
+        } else {
+            int32_t its = 0;
+            st = power_norm(&Sv, (int)(h->diag == FC_DIAG_UNIT), 1000, 1e-12, s, &h->spec_norm, &its);
+            if (st != FC_OK)
+                return cleanup(st);
+        }
         h->L_thm = 4.0 * h->spec_norm + 12.0 * (double)h->n;
     }
 
@@ -895,6 +915,16 @@ fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_d
         return cleanup(status_of(h));
     *out = h;
     return FC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_dtype u0_dtype,
+                    void *stream, fc_solver **out) {
+    g_last_error.clear();
+    return create_impl(S, opt, U0, u0_dtype, (hipStream_t)stream, 65536, false, out);
 }
 
 fc_status fc_step(fc_solver *h, int32_t iters, fc_info *info) {
