@@ -41,11 +41,27 @@ template <> struct Acc4<double> { typedef doublex4 type; };
 __device__ __forceinline__ floatx4 mfma16x16x4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+// The double version keeps the same lane contract, computed with cross-lane
+// reads and FP64 FMAs: lane (r, g) needs A[4g+q][k] (held by lane 16k+4g+q)
+// and B[k][r] (held by lane 16k+r).  It is used by the FP64 solver only.
 __device__ __forceinline__ doublex4 mfma16x16x4(double a, double b, doublex4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const double bk = __shfl(b, 16 * k + r, 64);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            c[q] = fma(__shfl(a, 16 * k + 4 * g + q, 64), bk, c[q]);
+    }
+    return c;
 }
 
 template <typename T> __device__ __forceinline__ float to_f32(T v) { return (float)v; }
+// A stored value in the accumulation type TA (double stays double).
+template <typename TA, typename VS> __device__ __forceinline__ TA to_acc(VS v) {
+    return (TA)to_f32(v);
+}
+template <> __device__ __forceinline__ double to_acc<double, double>(double v) { return v; }
 template <> __device__ __forceinline__ float to_f32<__half>(__half v) { return __half2float(v); }
 template <> __device__ __forceinline__ float to_f32<__hip_bfloat16>(__hip_bfloat16 v) {
     return __bfloat162float(v);
@@ -117,7 +133,8 @@ struct Inst {
     int64_t n;
     int32_t c;
     int32_t diag_unit;
-    int64_t heavy_thr, nchunks, nheavy;
+    int64_t light_max, nmed, nchunks, nheavy;
+    const int32_t *med_rows;
     const int32_t *chunk_row;
     const int64_t *chunk_beg;
     const int32_t *chunk_len;
@@ -331,7 +348,7 @@ __global__ void k_check_csr(const int64_t *__restrict__ row_ptr, const int32_t *
                     const int64_t mid = (lo + hi) >> 1;
                     const int32_t cm = col[mid];
                     if (cm == (int32_t)i) {
-                        found = to_f32(val[mid]) == to_f32(val[k]);
+                        found = to_acc<double>(val[mid]) == to_acc<double>(val[k]);
                         break;
                     }
                     if (cm < (int32_t)i)
@@ -370,13 +387,24 @@ template <> struct Vec16<__hip_bfloat16> {
     static constexpr int N = 8;
 };
 
-template <typename TU, int CP> struct SpmmCfg {
+// A team of lanes working on one row: GS lanes per nonzero (16 bytes each),
+// SLOTS nonzeros side by side.
+template <typename TU, int CP, int WANT_SLOTS> struct TeamCfg {
     static constexpr int VEC = Vec16<TU>::N;
     static constexpr int GS = CP / VEC > 0 ? CP / VEC : 1;
-    static constexpr int TEAM = GS * 8 > 64 ? 64 : GS * 8;
+    static constexpr int TEAM = GS * WANT_SLOTS > 64 ? 64 : GS * WANT_SLOTS;
     static constexpr int SLOTS = TEAM / GS;
-    static constexpr int ROWS_PER_WG = 256 / TEAM;
+    static constexpr int TEAMS = 256 / TEAM;     // teams per 256-thread workgroup
     static constexpr int LANE_ELEMS = CP / GS;  // elements of the row handled per lane
+};
+// Short rows (at most SPMM_LIGHT_MAX nonzeros, most rows of a sparse graph)
+// get two-slot teams, so a wave works on several rows at once; longer rows
+// get whole waves of eight slots.
+constexpr int SPMM_LIGHT_MAX = 64;
+template <typename TU, int CP> struct SpmmCfg {
+    using Light = TeamCfg<TU, CP, 2>;
+    using Wide = TeamCfg<TU, CP, 8>;
+    static constexpr int ROWS_PER_WG = Light::TEAMS;
 };
 
 // Accumulator of LANE_ELEMS values in TA (float or double).
@@ -428,30 +456,28 @@ template <int NE> struct GatherLoad<__hip_bfloat16, NE> {
 template <typename T> struct AccumOf { typedef T type; };
 template <> struct AccumOf<__hip_bfloat16> { typedef float type; };
 
-// TU: type of the gathered rows (f64, f32 or bf16); TZ: output type;
 // Sum over the nonzeros e in [beg, end) of a row: a team of SLOTS slots takes
 // SLOTS * DEPTH nonzeros per pass, and every slot issues its DEPTH gathers
 // (predicated on e < end) before it consumes any of them, so a row shorter
 // than one pass costs a single memory round trip.
-template <typename TU, typename VS, int CP, int DEPTH, typename TA, int NE>
+template <typename TU, typename VS, int CP, int SLOTS, int DEPTH, typename TA, int NE>
 __device__ __forceinline__ void team_row_sum(const int32_t *__restrict__ col,
                                              const VS *__restrict__ val,
                                              const TU *__restrict__ U, int64_t beg, int64_t end,
                                              int slot, int sub, TA (&acc)[NE]) {
-    using Cfg = SpmmCfg<TU, CP>;
-    for (int64_t e0 = beg + slot; e0 < end; e0 += DEPTH * Cfg::SLOTS) {
+    for (int64_t e0 = beg + slot; e0 < end; e0 += DEPTH * SLOTS) {
         TA s[DEPTH];
         TA g[DEPTH][NE];
 #pragma unroll
         for (int u = 0; u < DEPTH; ++u) {
-            const int64_t e = e0 + u * Cfg::SLOTS;
+            const int64_t e = e0 + u * SLOTS;
             s[u] = (TA)0;
 #pragma unroll
             for (int q = 0; q < NE; ++q)
                 g[u][q] = (TA)0;
             if (e < end) {
                 const int64_t j = col[e];
-                s[u] = (TA)to_f32(val[e]);
+                s[u] = to_acc<TA>(val[e]);
                 GatherLoad<TU, NE>::load(U + j * CP + sub * NE, g[u]);
             }
         }
@@ -477,19 +503,52 @@ __device__ __forceinline__ void team_slot_sum(TA (&acc)[NE]) {
         }
 }
 
+// Row epilogue of a team whose slots are already summed: slot 0 adds u_i for
+// the unit diagonal, writes z_i and returns <u_i, z_i> on its sub-0 lane.
+template <int GS, typename TA, typename TZ, typename TX, int CP, int NE>
+__device__ __forceinline__ double row_epilogue(bool live, int slot, int sub, int64_t row,
+                                               const TX *__restrict__ X, TZ *__restrict__ Z,
+                                               int diag_unit, TA (&acc)[NE]) {
+    double d = 0.0;
+    if (live && slot == 0) {
+        TA xi[NE];
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            xi[q] = (TA)X[row * CP + sub * NE + q];
+        if (diag_unit)
+#pragma unroll
+            for (int q = 0; q < NE; ++q)
+                acc[q] += xi[q];
+#pragma unroll
+        for (int q = 0; q < NE; ++q) {
+            Z[row * CP + sub * NE + q] = (TZ)acc[q];
+            d += (double)acc[q] * (double)xi[q];
+        }
+    }
+#pragma unroll
+    for (int off = 1; off < GS; off <<= 1)
+        d += shfl_xor_d(d, off);
+    return (live && slot == 0 && sub == 0) ? d : 0.0;
+}
+
+// Z = S_eff U for one instance.
+//   light rows  (<= SPMM_LIGHT_MAX nonzeros): two-slot teams, in a
+//               grid-stride loop over blocks of ROWS_PER_WG rows;
+//   medium rows (listed in med_rows): one eight-slot team each;
+//   heavy rows  (listed as chunks of their nonzeros): each chunk summed by an
+//               eight-slot team into chunk_sum; k_combine adds a row's chunk
+//               sums in chunk order.
+// TU: type of the gathered rows (f64, f32 or bf16); TZ: output type;
 // TX: type of the row u_i used by the epilogue (the master copy);
 // VS: type of the stored values.
-//
-// Rows longer than heavy_thr nonzeros are not summed here: they are cut into
-// chunks (chunk_row, chunk_beg, chunk_len), each chunk is summed by one team
-// after the light rows, and k_spmm_combine adds the chunk sums of each heavy
-// row in chunk order.
 template <typename TU, typename TZ, typename TX, typename VS, int CP>
 __device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, int64_t nblk) {
-    using Cfg = SpmmCfg<TU, CP>;
+    using Lc = typename SpmmCfg<TU, CP>::Light;
+    using Wc = typename SpmmCfg<TU, CP>::Wide;
     using TA = typename AccumOf<TU>::type;
-    constexpr int NE = Cfg::LANE_ELEMS;
+    constexpr int NE = Lc::LANE_ELEMS;
     constexpr int DEPTH = 4;
+    static_assert(Lc::GS == Wc::GS, "both team shapes split a row the same way");
     const int slot_role = ring_slot(I, role);
     const TX *__restrict__ X = (const TX *)I.X[slot_role];
     TZ *__restrict__ Z = (TZ *)I.Z[slot_role];
@@ -498,68 +557,65 @@ __device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, 
     const int64_t *__restrict__ row_ptr = I.row_ptr;
     const int32_t *__restrict__ col = I.col;
     const VS *__restrict__ val = (const VS *)I.val;
-    const int64_t n = I.n, heavy_thr = I.heavy_thr, nchunks = I.nchunks;
+    const int64_t n = I.n, light_max = I.light_max;
     const int diag_unit = I.diag_unit;
-    const int64_t *__restrict__ chunk_beg = I.chunk_beg;
-    const int32_t *__restrict__ chunk_len = I.chunk_len;
-    TA *__restrict__ chunk_sum = (TA *)I.chunk_sum;
-
     const int tid = threadIdx.x;
-    const int team = tid / Cfg::TEAM, lt = tid % Cfg::TEAM;
-    const int slot = lt / Cfg::GS, sub = lt % Cfg::GS;
     double trace_acc = 0.0;
-    const int64_t nblocks = (n + Cfg::ROWS_PER_WG - 1) / Cfg::ROWS_PER_WG;
-    for (int64_t rb = blk; rb < nblocks; rb += nblk) {
-        const int64_t row = rb * Cfg::ROWS_PER_WG + team;
-        TA acc[NE];
-#pragma unroll
-        for (int q = 0; q < NE; ++q)
-            acc[q] = (TA)0;
-        bool live = row < n;
-        if (live) {
-            const int64_t beg = row_ptr[row], end = row_ptr[row + 1];
-            if (end - beg > heavy_thr)
-                live = false;
-            else
-                team_row_sum<TU, VS, CP, DEPTH>(col, val, U, beg, end, slot, sub, acc);
-        }
-        team_slot_sum<Cfg::GS, Cfg::TEAM>(acc);
-        double d = 0.0;
-        if (live && slot == 0) {
-            TA xi[NE];
+
+    {   // light rows
+        const int team = tid / Lc::TEAM, lt = tid % Lc::TEAM;
+        const int slot = lt / Lc::GS, sub = lt % Lc::GS;
+        const int64_t nblocks = (n + Lc::TEAMS - 1) / Lc::TEAMS;
+        for (int64_t rb = blk; rb < nblocks; rb += nblk) {
+            const int64_t row = rb * Lc::TEAMS + team;
+            TA acc[NE];
 #pragma unroll
             for (int q = 0; q < NE; ++q)
-                xi[q] = (TA)X[row * CP + sub * NE + q];
-            if (diag_unit)
+                acc[q] = (TA)0;
+            bool live = row < n;
+            if (live) {
+                const int64_t beg = row_ptr[row], end = row_ptr[row + 1];
+                if (end - beg > light_max)
+                    live = false;
+                else
+                    team_row_sum<TU, VS, CP, Lc::SLOTS, DEPTH>(col, val, U, beg, end, slot, sub, acc);
+            }
+            team_slot_sum<Lc::GS, Lc::TEAM>(acc);
+            trace_acc += row_epilogue<Lc::GS, TA, TZ, TX, CP>(live, slot, sub, row, X, Z, diag_unit, acc);
+        }
+    }
+    {   // medium rows, then the chunks of heavy rows
+        const int team = tid / Wc::TEAM, lt = tid % Wc::TEAM;
+        const int slot = lt / Wc::GS, sub = lt % Wc::GS;
+        const int32_t *__restrict__ med_rows = I.med_rows;
+        for (int64_t m = blk * Wc::TEAMS + team; m < I.nmed; m += nblk * Wc::TEAMS) {
+            const int64_t row = med_rows[m];
+            TA acc[NE];
+#pragma unroll
+            for (int q = 0; q < NE; ++q)
+                acc[q] = (TA)0;
+            team_row_sum<TU, VS, CP, Wc::SLOTS, DEPTH>(col, val, U, row_ptr[row], row_ptr[row + 1],
+                                                        slot, sub, acc);
+            team_slot_sum<Wc::GS, Wc::TEAM>(acc);
+            trace_acc += row_epilogue<Wc::GS, TA, TZ, TX, CP>(true, slot, sub, row, X, Z, diag_unit, acc);
+        }
+        const int64_t *__restrict__ chunk_beg = I.chunk_beg;
+        const int32_t *__restrict__ chunk_len = I.chunk_len;
+        TA *__restrict__ chunk_sum = (TA *)I.chunk_sum;
+        for (int64_t k = blk * Wc::TEAMS + team; k < I.nchunks; k += nblk * Wc::TEAMS) {
+            TA acc[NE];
+#pragma unroll
+            for (int q = 0; q < NE; ++q)
+                acc[q] = (TA)0;
+            const int64_t beg = chunk_beg[k];
+            team_row_sum<TU, VS, CP, Wc::SLOTS, DEPTH>(col, val, U, beg, beg + chunk_len[k], slot, sub,
+                                                        acc);
+            team_slot_sum<Wc::GS, Wc::TEAM>(acc);
+            if (slot == 0)
 #pragma unroll
                 for (int q = 0; q < NE; ++q)
-                    acc[q] += xi[q];
-#pragma unroll
-            for (int q = 0; q < NE; ++q) {
-                Z[row * CP + sub * NE + q] = (TZ)acc[q];
-                d += (double)acc[q] * (double)xi[q];
-            }
+                    chunk_sum[k * CP + sub * NE + q] = acc[q];
         }
-#pragma unroll
-        for (int off = 1; off < Cfg::GS; off <<= 1)
-            d += shfl_xor_d(d, off);
-        if (live && slot == 0 && sub == 0)
-            trace_acc += d;
-    }
-    // chunks of heavy rows
-    constexpr int TEAMS = 256 / Cfg::TEAM;
-    for (int64_t k = blk * TEAMS + team; k < nchunks; k += nblk * TEAMS) {
-        TA acc[NE];
-#pragma unroll
-        for (int q = 0; q < NE; ++q)
-            acc[q] = (TA)0;
-        const int64_t beg = chunk_beg[k];
-        team_row_sum<TU, VS, CP, DEPTH>(col, val, U, beg, beg + chunk_len[k], slot, sub, acc);
-        team_slot_sum<Cfg::GS, Cfg::TEAM>(acc);
-        if (slot == 0)
-#pragma unroll
-            for (int q = 0; q < NE; ++q)
-                chunk_sum[k * CP + sub * NE + q] = acc[q];
     }
     __shared__ double sh[256];
     sh[tid] = trace_acc;

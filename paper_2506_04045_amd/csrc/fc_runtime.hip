@@ -103,15 +103,17 @@ void launch_reduce(const double *in, int64_t np, int64_t ld, int64_t ne, double 
     hipLaunchKernelGGL(k_reduce_cols, dim3(blocks), dim3(256), 0, s, in, np, ld, ne, out, eb);
 }
 
-// Rows with more than HEAVY_THR nonzeros are summed in chunks of HEAVY_CHUNK
-// nonzeros by whole teams and combined per row in chunk order.
+// Rows with more than SPMM_LIGHT_MAX nonzeros are summed by whole-wave teams:
+// up to HEAVY_THR directly (the medium-row list), beyond it in chunks of
+// HEAVY_CHUNK nonzeros combined per row in chunk order.
 constexpr int64_t HEAVY_THR = 2048;
-constexpr int64_t HEAVY_CHUNK = 2048;
+constexpr int64_t HEAVY_CHUNK = 1024;
 
 // Heavy-row plan built on the host from row_ptr.  Device arrays are owned
 // by `bufs` (stream-ordered frees).
 struct HeavyPlan {
-    int64_t nheavy = 0, nchunks = 0;
+    int64_t nheavy = 0, nchunks = 0, nmed = 0;
+    int32_t *med = nullptr;
     int32_t *rows = nullptr, *chunk_ptr = nullptr, *chunk_row = nullptr, *chunk_len = nullptr;
     int64_t *chunk_beg = nullptr;
     void *chunk_sum = nullptr;
@@ -138,12 +140,16 @@ fc_status build_heavy_plan(const int64_t *d_row_ptr, int64_t n, size_t acc_bytes
     std::vector<int64_t> rp(n + 1);
     HIPCHK(hipMemcpyAsync(rp.data(), d_row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    std::vector<int32_t> rows, cptr, crow, clen;
+    std::vector<int32_t> rows, cptr, crow, clen, med;
     std::vector<int64_t> cbeg;
     for (int64_t i = 0; i < n; ++i) {
         const int64_t len = rp[i + 1] - rp[i];
-        if (len <= HEAVY_THR)
+        if (len <= SPMM_LIGHT_MAX)
             continue;
+        if (len <= HEAVY_THR) {
+            med.push_back((int32_t)i);
+            continue;
+        }
         rows.push_back((int32_t)i);
         cptr.push_back((int32_t)cbeg.size());
         for (int64_t b = rp[i]; b < rp[i + 1]; b += HEAVY_CHUNK) {
@@ -156,6 +162,12 @@ fc_status build_heavy_plan(const int64_t *d_row_ptr, int64_t n, size_t acc_bytes
     cptr.push_back((int32_t)cbeg.size());
     plan.nheavy = (int64_t)rows.size();
     plan.nchunks = (int64_t)cbeg.size();
+    plan.nmed = (int64_t)med.size();
+    if (plan.nmed > 0) {
+        HIPCHK(plan.alloc(&plan.med, sizeof(int32_t) * med.size()));
+        HIPCHK(hipMemcpyAsync(plan.med, med.data(), sizeof(int32_t) * med.size(), hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     if (plan.nheavy == 0)
         return FC_OK;
     HIPCHK(plan.alloc(&plan.rows, sizeof(int32_t) * rows.size()));
@@ -181,7 +193,9 @@ int combine_grid(int64_t nheavy, int rows_per_block) {
 
 // Copy the heavy-row plan into an instance descriptor.
 void plan_to_inst(const HeavyPlan &hp, Inst &I) {
-    I.heavy_thr = hp.nheavy > 0 ? HEAVY_THR : INT64_MAX;
+    I.light_max = SPMM_LIGHT_MAX;
+    I.nmed = hp.nmed;
+    I.med_rows = hp.med;
     I.nchunks = hp.nchunks;
     I.nheavy = hp.nheavy;
     I.chunk_row = hp.chunk_row;
@@ -1414,14 +1428,14 @@ fc_status fc_gram(const void *U, fc_dtype dtype, int64_t n, int32_t c, void *str
 fc_status fc_project(const void *V, void *out, fc_dtype dtype, int64_t rows, int32_t c, int64_t ld,
                      void *stream) {
     g_last_error.clear();
-    if (!V || !out)
-        return fail(FC_ERR_INVALID_ARG, "V or out is NULL");
     if (rows < 0 || c < 1 || c > 64 || ld < c)
         return fail(FC_ERR_INVALID_ARG, "need rows >= 0, c in [1, 64], ld >= c");
     if (dtype != FC_F64 && dtype != FC_F32)
         return fail(FC_ERR_INVALID_ARG, "dtype must be FC_F64 or FC_F32");
     if (rows == 0)
         return FC_OK;
+    if (!V || !out)
+        return fail(FC_ERR_INVALID_ARG, "V or out is NULL");
     hipStream_t s = (hipStream_t)stream;
     const int cpm = cpm_of(cp_of(c));
     const int cus = device_cus();

@@ -175,3 +175,20 @@ def test_spectral_norm(fc, diag):
     assert got == pytest.approx(ref, rel=1e-9)
     got32, _ = fc.spectral_norm(*csr_to_dev(rp, ci, v.astype(np.float32), torch.float32), diag=diag)
     assert got32 == pytest.approx(ref, rel=1e-6)
+
+
+def test_spmm_power_law_rows_of_every_class(fc):
+    """A power-law pattern has short rows (two-slot teams), medium rows
+    (65-2,048 nonzeros, whole-wave teams) and hub rows (chunked)."""
+    wl = W.chung_lu_planted(20000, 16, 20.0, 2.1, 50_000.0, 0.05, 3, val_dtype=torch.float64)
+    rp, ci, v, _ = wl.numpy()
+    deg = np.diff(rp)
+    assert (deg <= 64).any() and ((deg > 64) & (deg <= 2048)).any() and (deg > 2048).any()
+    U = np.random.default_rng(4).random((wl.n, 16))
+    ref = oracle.x_s(rp, ci, v, True, U)
+    z = fc.spmm(*csr_to_dev(rp, ci, v, torch.float64), dev(U, torch.float64)).cpu().numpy()
+    assert normwise(z, ref) <= 1e-13
+    v32, U32 = v.astype(np.float32), U.astype(np.float32)
+    ref32 = oracle.x_s(rp, ci, v32.astype(np.float64), True, U32.astype(np.float64))
+    z32 = fc.spmm(*csr_to_dev(rp, ci, v32, torch.float32), dev(U32)).cpu().numpy()
+    assert normwise(z32, ref32) <= 1e-5

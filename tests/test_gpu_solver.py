@@ -298,3 +298,22 @@ def test_checkpoint_resume_is_bitwise(fc, backtrack):
     with fc.Solver(S.row_ptr, S.col_idx, S.val, 8, None, step=1e-3) as d:
         with pytest.raises(_native.FcError):
             d.set_state(state)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_power_law_instance_follows_the_oracle(fc, prec):
+    wl = W.chung_lu_planted(20000, 16, 20.0, 2.1, 50_000.0, 0.05, 5,
+                            val_dtype=torch.float64, u_dtype=torch.float64)
+    rp, ci, v, U0 = wl.numpy()
+    if prec == "fp32":
+        v = v.astype(np.float32).astype(np.float64)
+        U0 = U0.astype(np.float32).astype(np.float64)
+    spec, _ = oracle.spectral_norm(rp, ci, v, True)
+    tau = 20.0 / oracle.lipschitz_bound(spec, wl.n)
+    ref = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=40, step=tau)
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, 16, prec, 40, step=tau)
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    print(f"power-law {prec}: f_rel={abs(info.f - ref.f[-1]) / abs(ref.f[-1]):.2e} "
+          f"max|dU|={np.abs(U - ref.X).max():.2e}")
+    assert np.abs(U - ref.X).max() <= tol
+    assert abs(info.f - ref.f[-1]) <= tol * abs(ref.f[-1])
