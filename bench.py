@@ -111,7 +111,20 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1_000_000)
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--calibrate-copy-mb", type=int, default=0,
+                    help="only run a plain elementwise copy of this many MiB (read + write), "
+                         "the reference for scaling HBM byte counters")
     args = ap.parse_args()
+    if args.calibrate_copy_mb:
+        import torch
+        x = torch.ones(args.calibrate_copy_mb * (1 << 18), device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(5):
+            torch.mul(x, 1.0, out=y)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "elementwise copy", "bytes_read_per_launch": x.numel() * 4,
+                          "bytes_written_per_launch": y.numel() * 4, "launches": 5}))
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

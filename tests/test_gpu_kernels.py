@@ -95,7 +95,7 @@ def test_spmm_fp64_and_fp32(fc, diag, c):
 
 
 def test_spmm_heavy_row_and_empty_rows(fc):
-    rp, ci, v = star_plus_er(5000, 3.0, 1)
+    rp, ci, v = star_plus_er(5000, 3.0, 1, hub_frac=0.9)
     deg = np.diff(rp)
     assert deg.max() >= 4000 and (deg == 0).sum() > 0
     U = np.random.default_rng(2).random((5000, 32))
