@@ -98,6 +98,84 @@ def cpu_baseline(args, c: int, n_full: int, nnz_full: int) -> dict:
                        f"{dt:.3f} s/iteration scaled by nnz x{scale:.1f} to the full instance")}
 
 
+SERVE_SOLVE = dict(backtrack=True, tol_pgrad=1e-4, max_iter=300, norm_estimate="frobenius",
+                   check_every=16)
+
+
+def percentile(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs), q)) if len(xs) else None
+
+
+def serve_bench(args) -> dict:
+    """Served solves/s and latency against sequential plain FP32 solves on the
+    same Poisson arrival trace.  Requests: n log-uniform in [500, 2e5], c in
+    {4, 8, 16, 32, 64}, ER pattern of average degree U(10, 40), planted
+    communities; each solved by backtracking FISTA until r_n <= 1e-4 r_1 or
+    300 iterations.  The sequential baseline's latencies come from its measured
+    service times replayed through a first-come-first-served queue."""
+    import numpy as np
+    import torch
+    import paper_2506_04045_amd as fc
+    import workloads as W
+    R = args.serve_requests
+    log(f"serving: generating {R} requests on the GPU")
+    reqs = [W.serving_request(i, device="cuda") for i in range(R)]
+    torch.cuda.synchronize()
+    # sequential plain FP32 solves, FIFO
+    log("serving: sequential baseline")
+    service, f_seq = [], []
+    for wl in reqs:
+        t0 = time.perf_counter()
+        with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, **SERVE_SOLVE) as s:
+            info = s.solve()
+        service.append(time.perf_counter() - t0)
+        f_seq.append(info.f)
+    mu_seq = R / sum(service)
+    lam = args.serve_load * mu_seq
+    rng = np.random.default_rng(args.seed + 17)
+    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=R))
+    fin, t_free = [], 0.0
+    for a, s_ in zip(arrivals, service):
+        t_free = max(a, t_free) + s_
+        fin.append(t_free)
+    lat_seq = np.asarray(fin) - arrivals
+    log(f"serving: sequential {mu_seq:.1f} solves/s; arrivals at {lam:.1f}/s")
+    # served run in real time on the same trace
+    done = {}
+    with fc.Server(max_active=args.serve_slots, hbm_budget=args.serve_budget_gb * 2**30,
+                   ticks_per_poll=4) as sv:
+        t_start = fc.Server.clock()
+        k = 0
+        while len(done) < R:
+            now = fc.Server.clock() - t_start
+            while k < R and arrivals[k] <= now:
+                wl = reqs[k]
+                sv.submit(k, wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, **SERVE_SOLVE)
+                k += 1
+            wait = 200 if k >= R else max(0, min(2000, int((arrivals[k] - now) * 1e6)))
+            for r in sv.poll(256, timeout_us=wait):
+                done[r.req_id] = r
+                sv.release(r.req_id)
+            if fc.Server.clock() - t_start > args.serve_timeout:
+                raise RuntimeError("serving did not finish in time")
+    lat = np.asarray([done[i].t_finish - (t_start + arrivals[i]) for i in range(R)])
+    makespan = max(done[i].t_finish for i in range(R)) - (t_start + arrivals[0])
+    same = sum(1 for i in range(R) if done[i].f == f_seq[i])
+    iters = [done[i].iter for i in range(R)]
+    return {
+        "requests": R, "arrival_rate_per_s": lam, "load_vs_sequential": args.serve_load,
+        "served": {"solves_per_s": R / makespan, "p50_ms": 1e3 * percentile(lat, 50),
+                   "p99_ms": 1e3 * percentile(lat, 99), "slots": args.serve_slots},
+        "sequential_fp32": {"solves_per_s": mu_seq, "p50_ms": 1e3 * percentile(lat_seq, 50),
+                            "p99_ms": 1e3 * percentile(lat_seq, 99)},
+        "speedup_solves_per_s": (R / makespan) / mu_seq,
+        "results_identical_to_sequential": same,
+        "mean_iterations": float(np.mean(iters)),
+        "failed": sum(1 for r in done.values() if r.status != 0),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -111,6 +189,15 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1_000_000)
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--serve-requests", type=int, default=256,
+                    help="requests of the serving measurement (0 disables it)")
+    ap.add_argument("--serve-only", action="store_true",
+                    help="run only the serving measurement and print its JSON line")
+    ap.add_argument("--serve-load", type=float, default=2.0,
+                    help="arrival rate as a multiple of the sequential solve rate")
+    ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-timeout", type=float, default=600.0)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain elementwise copy of this many MiB (read + write), "
                          "the reference for scaling HBM byte counters")
@@ -140,6 +227,10 @@ def main() -> int:
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     log(f"library {fc.library_path()}")
+    if args.serve_only:
+        out = {"metric": METRIC, "serving": serve_bench(args)}
+        print(json.dumps(out), flush=True)
+        return 0
     t0 = time.perf_counter()
     log(f"generating the power-law workload n={args.n:,} c={args.c} on the GPU")
     wl = W.chung_lu_planted(args.n, args.c, 20.0, 2.1, 50_000.0, 0.05, args.seed, device="cuda")
@@ -185,10 +276,17 @@ def main() -> int:
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": kernels[dom]["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic}
 
+    del wl
+    torch.cuda.empty_cache()
+    serving = None
+    if args.serve_requests > 0:
+        serving = serve_bench(args)
+        log(f"serving: {serving['served']['solves_per_s']:.1f} solves/s (p99 "
+            f"{serving['served']['p99_ms']:.1f} ms) vs sequential "
+            f"{serving['sequential_fp32']['solves_per_s']:.1f} solves/s (p99 "
+            f"{serving['sequential_fp32']['p99_ms']:.1f} ms)")
     cpu = None
     if not args.no_cpu_baseline:
-        del wl
-        torch.cuda.empty_cache()
         cpu = cpu_baseline(args, c, n, nnz)
         log(f"cpu baseline {cpu['value']:.3e} iters/s on {cpu['cores']} threads")
 
@@ -217,6 +315,7 @@ def main() -> int:
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "serving": serving,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -247,6 +247,75 @@ fc_status fc_spectral_norm(const fc_csr *S, fc_diag diag, int32_t max_iter,
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *fc_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of many solves of problem (P) on one GPU.
+ *
+ * fc_server_submit queues a solve (any n and c <= 64; FP32; FISTA with a
+ * fixed step or backtracking; stop rules as in fc_options).  A worker thread
+ * admits queued requests in arrival order while the device memory held by
+ * admitted requests stays within hbm_budget and fewer than max_active are
+ * running; it sets each one up on its own stream, then advances all running
+ * requests together, one trial per tick, with batched kernels grouped by
+ * padded c and step rule.  A request gets exactly the arithmetic of fc_create
+ * + fc_solve with the same options, so its result does not depend on what
+ * it is batched with.  Finished requests wait in the server (holding their
+ * memory) until fc_server_release.
+ * ------------------------------------------------------------------------ */
+typedef struct fc_server fc_server;
+
+typedef struct {
+    uint32_t struct_size;   /* sizeof(fc_server_opts), set by fc_server_opts_default */
+    int32_t max_active;     /* requests iterating at once (default 64) */
+    double hbm_budget;      /* bytes of device memory admitted requests may hold
+                               (default 32 GiB); a request larger than the whole
+                               budget finishes with FC_ERR_OUT_OF_MEMORY */
+    int32_t ticks_per_poll; /* trials launched between reads of the request states
+                               (default 8) */
+    int32_t use_graph;      /* 1: replay each tick from a captured hipGraph (default) */
+} fc_server_opts;
+
+typedef struct {
+    uint64_t req_id;
+    int32_t status;         /* fc_status of the solve */
+    int32_t iter;           /* accepted iterations */
+    int32_t trials;
+    int32_t stop_reason;    /* fc_stop_reason */
+    double f;               /* final loss */
+    double t_submit, t_admit, t_finish;  /* seconds on fc_server_clock() */
+} fc_result;
+
+void fc_server_opts_default(fc_server_opts *opts);
+double fc_server_clock(void);
+
+/* Start a server; `stream` (hipStream_t, NULL = a new stream) carries the
+ * batched ticks.  Errors: FC_ERR_INVALID_ARG, FC_ERR_DEVICE. */
+fc_status fc_server_create(const fc_server_opts *opts, void *stream, fc_server **out);
+
+/* Queue one solve.  S (device CSR, FC_F32 values) and U0 (device n x c,
+ * FC_F32 or FC_F64, NULL = 1/c) are borrowed until the request's result has
+ * been released.  opt must ask for FC_PREC_FP32 and accelerate = 1 and no
+ * step schedule (FC_ERR_UNSUPPORTED otherwise).  req_id must be unique among
+ * requests not yet released.  Does not block. */
+fc_status fc_server_submit(fc_server *sv, const fc_csr *S, const fc_options *opt,
+                           const void *U0, fc_dtype u0_dtype, uint64_t req_id);
+
+/* Up to `max` results of finished requests not reported before, waiting up
+ * to timeout_us microseconds for at least one; *n_out receives the count. */
+fc_status fc_server_poll(fc_server *sv, fc_result *out, int32_t max, int32_t timeout_us,
+                         int32_t *n_out);
+
+/* Copy a finished request's memberships (n x c) to U_out (device); blocks
+ * until the copy is done.  fc_server_release frees the request's memory. */
+fc_status fc_server_get_u(fc_server *sv, uint64_t req_id, void *U_out, fc_dtype dtype);
+fc_status fc_server_release(fc_server *sv, uint64_t req_id);
+
+/* Queue lengths and the device memory held by admitted requests. */
+fc_status fc_server_stats(fc_server *sv, int32_t *n_pending, int32_t *n_active,
+                          int64_t *n_done, double *bytes_in_use);
+
+/* Stop the worker and free everything, including unreleased results. */
+void fc_server_destroy(fc_server *sv);
+
 #ifdef __cplusplus
 }
 #endif

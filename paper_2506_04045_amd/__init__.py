@@ -19,7 +19,7 @@ import torch
 
 from . import _native as N
 
-__all__ = ["Solver", "Info", "objective", "project", "spmm", "gram", "spectral_norm",
+__all__ = ["Solver", "Server", "Info", "objective", "project", "spmm", "gram", "spectral_norm",
            "library_path"]
 
 _PREC = {"fp64": N.FC_PREC_FP64, "fp32": N.FC_PREC_FP32, "mixed": N.FC_PREC_MIXED}
@@ -87,6 +87,29 @@ class Info:
                     i.pgrad_rel)
 
 
+def _options(c: int, precision: str = "fp32", diag: str = "unit", accelerate: bool = True,
+             step: float = 0.0, backtrack: bool = False, L0: float = 0.0, eta: float = 2.0,
+             max_iter: int = 100, check_every: int = 16, tol_loss: float = math.nan,
+             tol_pgrad: float = 0.0, validate: bool = False,
+             norm_estimate: str = "power") -> N.Options:
+    opt = N.default_options()
+    opt.c = int(c)
+    opt.precision = _PREC[precision]
+    opt.diag = _DIAG[diag]
+    opt.accelerate = int(bool(accelerate))
+    opt.step_rule = N.FC_STEP_BACKTRACK if backtrack else N.FC_STEP_FIXED
+    opt.step = float(step)
+    opt.L0 = float(L0)
+    opt.eta = float(eta)
+    opt.max_iter = int(max_iter)
+    opt.check_every = int(check_every)
+    opt.tol_loss = float(tol_loss)
+    opt.tol_pgrad = float(tol_pgrad)
+    opt.validate = int(bool(validate))
+    opt.norm_estimate = {"power": 0, "frobenius": 1}[norm_estimate]
+    return opt
+
+
 class Solver:
     """One solve of problem (P): fc_create / fc_step / fc_solve / fc_get_u."""
 
@@ -100,21 +123,8 @@ class Solver:
         self._csr = _CsrView(row_ptr, col_idx, val)
         self.n, self.c = self._csr.n, int(c)
         self.precision = precision
-        opt = N.default_options()
-        opt.c = self.c
-        opt.precision = _PREC[precision]
-        opt.diag = _DIAG[diag]
-        opt.accelerate = int(bool(accelerate))
-        opt.step_rule = N.FC_STEP_BACKTRACK if backtrack else N.FC_STEP_FIXED
-        opt.step = float(step)
-        opt.L0 = float(L0)
-        opt.eta = float(eta)
-        opt.max_iter = int(max_iter)
-        opt.check_every = int(check_every)
-        opt.tol_loss = float(tol_loss)
-        opt.tol_pgrad = float(tol_pgrad)
-        opt.validate = int(bool(validate))
-        opt.norm_estimate = {"power": 0, "frobenius": 1}[norm_estimate]
+        opt = _options(c, precision, diag, accelerate, step, backtrack, L0, eta, max_iter,
+                       check_every, tol_loss, tol_pgrad, validate, norm_estimate)
         self._sched = None
         if step_schedule is not None:
             self._sched = np.ascontiguousarray(step_schedule, dtype=np.float64)
@@ -195,6 +205,96 @@ class Solver:
         if self._h is not None:
             N.load().fc_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+@dataclass
+class Result:
+    req_id: int
+    status: int
+    iter: int
+    trials: int
+    stop_reason: int
+    f: float
+    t_submit: float
+    t_admit: float
+    t_finish: float
+
+
+class Server:
+    """Continuous-batching server (fc_server_*).  Submitted tensors are
+    borrowed until the request is released."""
+
+    def __init__(self, max_active: int = 64, hbm_budget: float = 32.0 * 2**30,
+                 ticks_per_poll: int = 8, use_graph: bool = True, stream=None):
+        lib = N.load()
+        o = N.default_server_options()
+        o.max_active = int(max_active)
+        o.hbm_budget = float(hbm_budget)
+        o.ticks_per_poll = int(ticks_per_poll)
+        o.use_graph = int(bool(use_graph))
+        h = ctypes.c_void_p()
+        N.check(lib.fc_server_create(ctypes.byref(o), None if stream is None
+                                     else int(stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    @staticmethod
+    def clock() -> float:
+        return float(N.load().fc_server_clock())
+
+    def submit(self, req_id: int, row_ptr, col_idx, val, c: int, U0=None, **options) -> None:
+        csr = _CsrView(row_ptr, col_idx, val)
+        opt = _options(c, **options)
+        u0_ptr, u0_dt = None, N.FC_F32
+        if U0 is not None:
+            U0 = _dev(U0, "U0", (torch.float64, torch.float32))
+            u0_ptr, u0_dt = U0.data_ptr(), _DT[U0.dtype]
+        N.check(N.load().fc_server_submit(self._h, ctypes.byref(csr.c), ctypes.byref(opt),
+                                          u0_ptr, u0_dt, int(req_id)))
+        self._keep[int(req_id)] = (csr, U0, csr.n, int(c))
+
+    def poll(self, max_results: int = 256, timeout_us: int = 0) -> list:
+        buf = (N.Result * max_results)()
+        cnt = ctypes.c_int32(0)
+        N.check(N.load().fc_server_poll(self._h, buf, max_results, int(timeout_us),
+                                        ctypes.byref(cnt)))
+        return [Result(r.req_id, r.status, r.iter, r.trials, r.stop_reason, r.f, r.t_submit,
+                       r.t_admit, r.t_finish) for r in buf[: cnt.value]]
+
+    def get_u(self, req_id: int, dtype=torch.float32) -> torch.Tensor:
+        _, _, n, c = self._keep[int(req_id)]
+        out = torch.empty(n, c, dtype=dtype, device="cuda")
+        N.check(N.load().fc_server_get_u(self._h, int(req_id), out.data_ptr(), _DT[dtype]))
+        return out
+
+    def release(self, req_id: int) -> None:
+        N.check(N.load().fc_server_release(self._h, int(req_id)))
+        self._keep.pop(int(req_id), None)
+
+    def stats(self) -> dict:
+        p, a = ctypes.c_int32(), ctypes.c_int32()
+        d, b = ctypes.c_int64(), ctypes.c_double()
+        N.check(N.load().fc_server_stats(self._h, ctypes.byref(p), ctypes.byref(a),
+                                         ctypes.byref(d), ctypes.byref(b)))
+        return dict(pending=p.value, active=a.value, done=d.value, bytes_in_use=b.value)
+
+    def close(self) -> None:
+        if self._h is not None:
+            N.load().fc_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
 
     def __del__(self):
         try:

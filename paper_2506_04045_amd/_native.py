@@ -29,6 +29,9 @@ EXPORTED = [
     "fc_options_default", "fc_create", "fc_step", "fc_step_profiled", "fc_solve", "fc_get_u", "fc_get_history",
     "fc_get_state", "fc_set_state", "fc_destroy", "fc_objective", "fc_project", "fc_spmm",
     "fc_gram", "fc_spectral_norm", "fc_last_error",
+    "fc_server_opts_default", "fc_server_clock", "fc_server_create", "fc_server_submit",
+    "fc_server_poll", "fc_server_get_u", "fc_server_release", "fc_server_stats",
+    "fc_server_destroy",
 ]
 
 
@@ -62,6 +65,20 @@ class KernelTimes(ctypes.Structure):
     _fields_ = [("fused_ms", ctypes.c_double), ("spmm_ms", ctypes.c_double),
                 ("reduce_ms", ctypes.c_double), ("control_ms", ctypes.c_double),
                 ("launches", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_active", ctypes.c_int32),
+                ("hbm_budget", ctypes.c_double), ("ticks_per_poll", ctypes.c_int32),
+                ("use_graph", ctypes.c_int32)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("iter", ctypes.c_int32), ("trials", ctypes.c_int32),
+                ("stop_reason", ctypes.c_int32), ("f", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_finish", ctypes.c_double)]
 
 
 _lib = None
@@ -114,6 +131,26 @@ def load() -> ctypes.CDLL:
     lib.fc_spectral_norm.restype = st
     lib.fc_last_error.argtypes = []
     lib.fc_last_error.restype = ctypes.c_char_p
+    lib.fc_server_opts_default.argtypes = [P]
+    lib.fc_server_opts_default.restype = None
+    lib.fc_server_clock.argtypes = []
+    lib.fc_server_clock.restype = f64
+    lib.fc_server_create.argtypes = [ctypes.POINTER(ServerOpts), P, ctypes.POINTER(P)]
+    lib.fc_server_create.restype = st
+    lib.fc_server_submit.argtypes = [P, ctypes.POINTER(CSR), ctypes.POINTER(Options), P,
+                                     ctypes.c_int, ctypes.c_uint64]
+    lib.fc_server_submit.restype = st
+    lib.fc_server_poll.argtypes = [P, ctypes.POINTER(Result), i32, i32, ctypes.POINTER(i32)]
+    lib.fc_server_poll.restype = st
+    lib.fc_server_get_u.argtypes = [P, ctypes.c_uint64, P, ctypes.c_int]
+    lib.fc_server_get_u.restype = st
+    lib.fc_server_release.argtypes = [P, ctypes.c_uint64]
+    lib.fc_server_release.restype = st
+    lib.fc_server_stats.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                    ctypes.POINTER(i64), ctypes.POINTER(f64)]
+    lib.fc_server_stats.restype = st
+    lib.fc_server_destroy.argtypes = [P]
+    lib.fc_server_destroy.restype = None
     _lib = lib
     return lib
 
@@ -128,6 +165,17 @@ def check(status: int) -> None:
     if status != FC_OK:
         msg = load().fc_last_error()
         raise FcError(status, msg.decode() if msg else "")
+
+
+def default_server_options() -> ServerOpts:
+    lib = load()
+    raw = (ctypes.c_char * 256)()
+    lib.fc_server_opts_default(ctypes.cast(raw, ctypes.c_void_p))
+    size = ctypes.c_uint32.from_buffer(raw).value
+    if size != ctypes.sizeof(ServerOpts):
+        raise RuntimeError(f"fc_server_opts layout mismatch: C {size} vs ctypes "
+                           f"{ctypes.sizeof(ServerOpts)}")
+    return ServerOpts.from_buffer_copy(bytes(raw[:size]))
 
 
 def default_options() -> Options:

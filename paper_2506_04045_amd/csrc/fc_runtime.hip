@@ -14,14 +14,21 @@
 // the host only re-launches that sequence and reads the state back.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <climits>
 #include <cmath>
+#include <condition_variable>
 #include <cstddef>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
-#include "../../include/fc.h"
+#include "fc.h"
 #include "fc_kernels.hpp"
 
 using namespace fc;
@@ -1470,3 +1477,5 @@ fc_status fc_spectral_norm(const fc_csr *S, fc_diag diag, int32_t max_iter, doub
 }
 
 }  // extern "C"
+
+#include "fc_server.inc"
