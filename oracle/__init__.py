@@ -79,6 +79,7 @@ def _load():
         lib.fcref_norm_s_sq.restype = f64
         lib.fcref_x_s.argtypes = [i64, P, P, P, ctypes.c_int, ctypes.c_int, P, P]
         lib.fcref_share.argtypes = [i64, ctypes.c_int, P, P]
+        lib.fcref_x_s_rows.argtypes = [i64, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P]
         lib.fcref_project_simplex.argtypes = [ctypes.c_int, P, P]
         lib.fcref_project_columns.argtypes = [i64, ctypes.c_int, P, P]
         lib.fcref_loss.argtypes = [i64, P, P, P, ctypes.c_int, ctypes.c_int, P]
@@ -142,6 +143,34 @@ def share(X) -> np.ndarray:
     out = np.empty((C, C), dtype=np.float64)
     _load().fcref_share(X.shape[0], C, _ptr(X), _ptr(out))
     return out
+
+
+def x_s_rows(rows, sub_row_ptr, sub_col_idx, sub_val, diag_unit: bool, X) -> np.ndarray:
+    """X s_i (section 3, eq. gradient_column) for the listed articles only.
+    sub_row_ptr/sub_col_idx/sub_val hold the rows of S of those articles, in
+    the order of `rows`; X is the full (N, C) membership matrix."""
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    m, rp, ci, v = _csr(sub_row_ptr, sub_col_idx, sub_val)
+    if rows.shape[0] != m:
+        raise ValueError("one CSR row per listed article")
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    out = np.empty((m, X.shape[1]), dtype=np.float64)
+    _load().fcref_x_s_rows(m, _ptr(rows), _ptr(rp), _ptr(ci), _ptr(v), int(diag_unit),
+                           X.shape[1], _ptr(X), _ptr(out))
+    return out
+
+
+def step_rows(rows, sub_row_ptr, sub_col_idx, sub_val, diag_unit: bool, X, tau: float) -> np.ndarray:
+    """One projected gradient step X -> P_Omega(X - tau grad f(X)) (Alg. 2)
+    evaluated at the listed articles only: column i of the gradient is
+    -4 (X s_i - share x_i) (eq. gradient_column) with share = X X^T over all
+    N articles, and each updated column is projected onto the simplex (Alg. 1)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    G = share(X)
+    XS = x_s_rows(rows, sub_row_ptr, sub_col_idx, sub_val, diag_unit, X)
+    xr = X[np.asarray(rows, dtype=np.int64)]
+    grad = -4.0 * (XS - xr @ G)
+    return project_columns(xr - tau * grad)
 
 
 def project_simplex(x) -> np.ndarray:

@@ -22,8 +22,9 @@
  * hold no diagonal entry; with diag_unit = 0 the CSR arrays are S itself.
  *
  * Arithmetic is IEEE double throughout.  Reductions that combine values from
- * different columns run sequentially in column order, so every result is the
- * same for any number of OpenMP threads.
+ * different columns run in a fixed order (sequentially in column order, or in
+ * fixed blocks of consecutive columns added in block order), so every result
+ * is the same for any number of OpenMP threads.
  */
 #include <math.h>
 #include <stdint.h>
@@ -82,16 +83,62 @@ void fcref_x_s(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
     }
 }
 
-/* share = X X^T, the C x C matrix shared by all column updates (Alg. 2).
- * Plain sum of outer products over the columns, in column order. */
+/* share = X X^T, the C x C matrix shared by all column updates (Alg. 2):
+ * the sum of the outer products x_i x_i^T over the columns.  The columns are
+ * taken in blocks of SHARE_BLOCK consecutive indices; each block is summed in
+ * column order and the block sums are added in block order, so the result is
+ * the same for any number of threads. */
+#define SHARE_BLOCK 65536
 void fcref_share(int64_t n, int C, const double *X, double *share)
 {
-    memset(share, 0, sizeof(double) * (size_t)C * (size_t)C);
-    for (int64_t i = 0; i < n; ++i) {
-        const double *xi = X + i * C;
+    const int64_t nb = (n + SHARE_BLOCK - 1) / SHARE_BLOCK;
+    const size_t cc = (size_t)C * (size_t)C;
+    memset(share, 0, sizeof(double) * cc);
+    if (nb == 0)
+        return;
+    double *part = (double *)calloc((size_t)nb * cc, sizeof(double));
+    #pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t b = 0; b < nb; ++b) {
+        double *pb = part + (size_t)b * cc;
+        const int64_t end = (b + 1) * SHARE_BLOCK < n ? (b + 1) * SHARE_BLOCK : n;
+        for (int64_t i = b * SHARE_BLOCK; i < end; ++i) {
+            const double *xi = X + i * C;
+            for (int k = 0; k < C; ++k)
+                for (int l = 0; l < C; ++l)
+                    pb[k * C + l] += xi[k] * xi[l];
+        }
+    }
+    for (int64_t b = 0; b < nb; ++b)
+        for (size_t q = 0; q < cc; ++q)
+            share[q] += part[(size_t)b * cc + q];
+    free(part);
+}
+
+/* The products X s_i of eq. (gradient_column) for a list of m articles only:
+ * rows[r] is the article, and sub_row_ptr / sub_col_idx / sub_val hold that
+ * article's row of S (its column, S being symmetric) as entries
+ * sub_row_ptr[r] .. sub_row_ptr[r+1]-1 of the two arrays.  X is the full
+ * C x N membership matrix.  Output XS is m x C. */
+void fcref_x_s_rows(int64_t m, const int64_t *rows, const int64_t *sub_row_ptr,
+                    const int32_t *sub_col_idx, const double *sub_val, int diag_unit,
+                    int C, const double *X, double *XS)
+{
+    #pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < m; ++r) {
+        double *out = XS + r * C;
         for (int k = 0; k < C; ++k)
-            for (int l = 0; l < C; ++l)
-                share[k * C + l] += xi[k] * xi[l];
+            out[k] = 0.0;
+        for (int64_t e = sub_row_ptr[r]; e < sub_row_ptr[r + 1]; ++e) {
+            const double s = sub_val[e];
+            const double *xj = X + (int64_t)sub_col_idx[e] * C;
+            for (int k = 0; k < C; ++k)
+                out[k] += s * xj[k];
+        }
+        if (diag_unit) {
+            const double *xi = X + rows[r] * C;
+            for (int k = 0; k < C; ++k)
+                out[k] += xi[k];
+        }
     }
 }
 

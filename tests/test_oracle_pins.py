@@ -76,6 +76,50 @@ def test_x_s_is_the_sparse_product(O):
         assert np.allclose(O.x_s(rp, ci, v, diag_unit, U), S @ U, rtol=0, atol=1e-13)
 
 
+def test_share_is_the_gram_matrix_across_blocks(O):
+    """share = sum of outer products; the blocked sum spans several blocks and a
+    ragged tail (65,536 columns per block)."""
+    rng = np.random.default_rng(11)
+    U = rng.random((3 * 65536 + 77, 3))
+    G = O.share(U)
+    ref = np.zeros((3, 3))
+    for k in range(3):
+        for l in range(3):
+            ref[k, l] = math.fsum(U[:, k] * U[:, l])
+    assert np.abs(G - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.array_equal(G, G.T)
+
+
+def _sub_csr(rp, ci, v, rows):
+    sub_rp = [0]
+    sub_ci, sub_v = [], []
+    for r in rows:
+        sub_ci += list(ci[rp[r]:rp[r + 1]])
+        sub_v += list(v[rp[r]:rp[r + 1]])
+        sub_rp.append(len(sub_ci))
+    return np.array(sub_rp), np.array(sub_ci, dtype=np.int32), np.array(sub_v)
+
+
+@pytest.mark.parametrize("diag_unit", [False, True])
+def test_rows_subset_product_and_step_match_dense_definitions(O, diag_unit):
+    """x_s_rows is the product at a list of articles; step_rows is one
+    projected gradient step there (Alg. 2), checked against the dense
+    gradient by finite differences and the support-enumeration projection."""
+    rng = np.random.default_rng(12)
+    n, c = 10, 4
+    (rp, ci, v), A = pins.random_symmetric_csr(n, 0.4, rng)
+    S = A + (np.eye(n) if diag_unit else 0)
+    U = pins.random_simplex_rows(n, c, rng)
+    rows = np.array([7, 0, 3, 3, 9])
+    sub = _sub_csr(rp, ci, v, rows)
+    assert np.allclose(O.x_s_rows(rows, *sub, diag_unit, U), (S @ U)[rows], rtol=0, atol=1e-13)
+    tau = 0.05
+    grad = pins.central_difference_gradient(S, U)
+    for r, x in zip(rows, O.step_rows(rows, *sub, diag_unit, U, tau)):
+        y = pins.project_simplex_bruteforce(U[r] - tau * grad[r])
+        assert np.abs(x - y).max() <= 1e-7
+
+
 # --------------------------------------------------------------------------
 # projection onto the simplex (Alg. 1)
 # --------------------------------------------------------------------------

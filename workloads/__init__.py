@@ -355,6 +355,13 @@ def config_full_power_law(seed: int = 0, device="cpu", n: int = 70_000_000) -> W
     return chung_lu_planted(n, 32, 20.0, 2.1, 50_000.0, 0.05, seed, device=device)
 
 
+def config_mixed_full(seed: int = 0, device="cpu", n: int = 70_000_000) -> Workload:
+    """The medium generator at n=7e7: ER pattern of average degree 30
+    (~2.1e9 stored nnz), 32 overlapping communities, sigma=0.05, FP32 values
+    (the mixed-precision solver keeps its own FP16 copy)."""
+    return er_planted(n, 32, 30.0, 0.05, seed, device=device)
+
+
 def serving_request(req_id: int, device="cpu", base_seed: int = 0) -> Workload:
     """One serving request: n log-uniform in [500, 2e5], c in {4,8,16,32,64},
     average degree U(10, 40), planted communities, ER pattern."""
