@@ -109,11 +109,12 @@ def percentile(xs, q):
 
 def serve_bench(args) -> dict:
     """Served solves/s and latency against sequential plain FP32 solves on the
-    same Poisson arrival trace.  Requests: n log-uniform in [500, 2e5], c in
+    same Poisson arrival traces.  Requests: n log-uniform in [500, 2e5], c in
     {4, 8, 16, 32, 64}, ER pattern of average degree U(10, 40), planted
     communities; each solved by backtracking FISTA until r_n <= 1e-4 r_1 or
-    300 iterations.  The sequential baseline's latencies come from its measured
-    service times replayed through a first-come-first-served queue."""
+    300 iterations.  The sequential baseline is measured once (its service
+    time per request); its latencies at each load come from replaying those
+    service times through a first-come-first-served queue on the same trace."""
     import numpy as np
     import torch
     import paper_2506_04045_amd as fc
@@ -122,7 +123,6 @@ def serve_bench(args) -> dict:
     log(f"serving: generating {R} requests on the GPU")
     reqs = [W.serving_request(i, device="cuda") for i in range(R)]
     torch.cuda.synchronize()
-    # sequential plain FP32 solves, FIFO
     log("serving: sequential baseline")
     service, f_seq = [], []
     for wl in reqs:
@@ -132,47 +132,121 @@ def serve_bench(args) -> dict:
         service.append(time.perf_counter() - t0)
         f_seq.append(info.f)
     mu_seq = R / sum(service)
-    lam = args.serve_load * mu_seq
-    rng = np.random.default_rng(args.seed + 17)
-    arrivals = np.cumsum(rng.exponential(1.0 / lam, size=R))
-    fin, t_free = [], 0.0
-    for a, s_ in zip(arrivals, service):
-        t_free = max(a, t_free) + s_
-        fin.append(t_free)
-    lat_seq = np.asarray(fin) - arrivals
-    log(f"serving: sequential {mu_seq:.1f} solves/s; arrivals at {lam:.1f}/s")
-    # served run in real time on the same trace
-    done = {}
-    with fc.Server(max_active=args.serve_slots, hbm_budget=args.serve_budget_gb * 2**30,
-                   ticks_per_poll=4) as sv:
-        t_start = fc.Server.clock()
-        k = 0
-        while len(done) < R:
-            now = fc.Server.clock() - t_start
-            while k < R and arrivals[k] <= now:
-                wl = reqs[k]
-                sv.submit(k, wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, **SERVE_SOLVE)
-                k += 1
-            wait = 200 if k >= R else max(0, min(2000, int((arrivals[k] - now) * 1e6)))
-            for r in sv.poll(256, timeout_us=wait):
-                done[r.req_id] = r
-                sv.release(r.req_id)
-            if fc.Server.clock() - t_start > args.serve_timeout:
-                raise RuntimeError("serving did not finish in time")
-    lat = np.asarray([done[i].t_finish - (t_start + arrivals[i]) for i in range(R)])
-    makespan = max(done[i].t_finish for i in range(R)) - (t_start + arrivals[0])
-    same = sum(1 for i in range(R) if done[i].f == f_seq[i])
-    iters = [done[i].iter for i in range(R)]
+    log(f"serving: sequential {mu_seq:.1f} solves/s")
+    out = {"requests": R, "slots": args.serve_slots,
+           "sequential_fp32": {"solves_per_s": mu_seq}, "loads": []}
+    for li, load in enumerate(float(x) for x in str(args.serve_load).split(",")):
+        lam = load * mu_seq
+        rng = np.random.default_rng(args.seed + 17 + li)
+        arrivals = np.cumsum(rng.exponential(1.0 / lam, size=R))
+        fin, t_free = [], 0.0
+        for a, s_ in zip(arrivals, service):
+            t_free = max(a, t_free) + s_
+            fin.append(t_free)
+        lat_seq = np.asarray(fin) - arrivals
+        done = {}
+        with fc.Server(max_active=args.serve_slots, hbm_budget=args.serve_budget_gb * 2**30,
+                       ticks_per_poll=4) as sv:
+            t_start = fc.Server.clock()
+            k = 0
+            while len(done) < R:
+                now = fc.Server.clock() - t_start
+                while k < R and arrivals[k] <= now:
+                    wl = reqs[k]
+                    sv.submit(k, wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, **SERVE_SOLVE)
+                    k += 1
+                wait = 200 if k >= R else max(0, min(2000, int((arrivals[k] - now) * 1e6)))
+                for r in sv.poll(256, timeout_us=wait):
+                    done[r.req_id] = r
+                    sv.release(r.req_id)
+                if fc.Server.clock() - t_start > args.serve_timeout:
+                    raise RuntimeError("serving did not finish in time")
+        lat = np.asarray([done[i].t_finish - (t_start + arrivals[i]) for i in range(R)])
+        makespan = max(done[i].t_finish for i in range(R)) - (t_start + arrivals[0])
+        span_seq = float(fin[-1] - arrivals[0])
+        ent = {
+            "load_vs_sequential": load, "arrival_rate_per_s": lam,
+            "served": {"solves_per_s": R / makespan, "p50_ms": 1e3 * percentile(lat, 50),
+                       "p99_ms": 1e3 * percentile(lat, 99)},
+            "sequential_fp32": {"solves_per_s": R / span_seq,
+                                "p50_ms": 1e3 * percentile(lat_seq, 50),
+                                "p99_ms": 1e3 * percentile(lat_seq, 99)},
+            "results_identical_to_sequential": sum(1 for i in range(R) if done[i].f == f_seq[i]),
+            "mean_iterations": float(np.mean([done[i].iter for i in range(R)])),
+            "failed": sum(1 for r in done.values() if r.status != 0),
+        }
+        out["loads"].append(ent)
+        log(f"serving at {load}x: {ent['served']['solves_per_s']:.1f} solves/s (p50 "
+            f"{ent['served']['p50_ms']:.1f} ms, p99 {ent['served']['p99_ms']:.1f} ms) vs "
+            f"sequential {ent['sequential_fp32']['solves_per_s']:.1f} solves/s (p50 "
+            f"{ent['sequential_fp32']['p50_ms']:.1f} ms, p99 {ent['sequential_fp32']['p99_ms']:.1f} ms)")
+    return out
+
+
+def mixed_target_bench(args) -> dict:
+    """Mixed precision against plain FP32 at equal objective, on the ER
+    instance of average degree 30 at n = 7e7 (2.1e9 stored nonzeros, c = 32).
+    FP32 runs K iterations of FISTA with tau = 1/L_thm; mixed precision (FP16
+    values, bfloat16 gathered rows) starts from the same U0 with the same tau
+    and runs until its iterate's objective, evaluated on the FP32 values,
+    reaches f_FP32(K) + 1e-6 (f(U0) - f_FP32(K)).  Objective checks are not
+    timed."""
+    import torch
+    import paper_2506_04045_amd as fc
+    import workloads as W
+    K = args.target_iters
+    log(f"mixed target: generating the ER degree-30 workload n={args.n:,}")
+    wl = W.config_mixed_full(device="cuda", n=args.n)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()   # hand the generator's scratch back before the solvers allocate
+    log(f"mixed target: nnz={wl.nnz:,}")
+    # tau = 1/L_thm with ||S||_F for ||S||_2, as the paper's experiments do
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 32, wl.U0, precision="fp32", step=0.0,
+                   norm_estimate="frobenius", reorder=args.reorder) as s:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = s.step(K)
+        torch.cuda.synchronize()
+        t_fp32 = time.perf_counter() - t0
+        hist = s.history()
+        f0, f_k, tau = float(hist["f"][0]), float(info.f), float(hist["tau"][1])
+        U = s.get_u()
+        f_k_check = fc.objective(wl.row_ptr, wl.col_idx, wl.val, U)
+        del U
+    df = f0 - f_k
+    target = f_k_check + 1e-6 * df
+    log(f"mixed target: FP32 {K} iterations in {t_fp32:.2f} s, f={f_k_check:.9e}, target {target:.9e}")
+    elapsed, it, f_mixed = 0.0, 0, math.inf
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 32, wl.U0, precision="mixed", step=tau,
+                   reorder=args.reorder) as s:
+        chunk = max(1, K - 5)
+        while it < 2 * K:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            s.step(chunk)
+            torch.cuda.synchronize()
+            elapsed += time.perf_counter() - t0
+            it += chunk
+            U = s.get_u()
+            f_mixed = fc.objective(wl.row_ptr, wl.col_idx, wl.val, U)
+            del U
+            if f_mixed <= target:
+                break
+            chunk = 1
+    reached = f_mixed <= target
+    log(f"mixed target: mixed {'reached' if reached else 'did not reach'} it after {it} "
+        f"iterations in {elapsed:.2f} s (f={f_mixed:.9e})")
+    del wl
+    torch.cuda.empty_cache()
     return {
-        "requests": R, "arrival_rate_per_s": lam, "load_vs_sequential": args.serve_load,
-        "served": {"solves_per_s": R / makespan, "p50_ms": 1e3 * percentile(lat, 50),
-                   "p99_ms": 1e3 * percentile(lat, 99), "slots": args.serve_slots},
-        "sequential_fp32": {"solves_per_s": mu_seq, "p50_ms": 1e3 * percentile(lat_seq, 50),
-                            "p99_ms": 1e3 * percentile(lat_seq, 99)},
-        "speedup_solves_per_s": (R / makespan) / mu_seq,
-        "results_identical_to_sequential": same,
-        "mean_iterations": float(np.mean(iters)),
-        "failed": sum(1 for r in done.values() if r.status != 0),
+        "workload": (f"ER average degree 30, n={args.n:,}, c=32, planted communities sigma 0.05, "
+                     f"unit diagonal, FISTA tau=1/L_thm with ||S||_F, articles relabelled: "
+                     f"{args.reorder}"),
+        "target": "f <= f_FP32(K) + 1e-6 (f(U0) - f_FP32(K)), objective on the FP32 values",
+        "K": K, "fp32": {"iters": K, "seconds": t_fp32, "iters_per_s": K / t_fp32, "f": f_k_check},
+        "mixed": {"iters": it, "seconds": elapsed, "iters_per_s": it / elapsed, "f": f_mixed,
+                  "reached": reached},
+        "speedup_time_to_target": (t_fp32 / elapsed) if reached else None,
     }
 
 
@@ -185,6 +259,10 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=70_000_000)
     ap.add_argument("--c", type=int, default=32)
     ap.add_argument("--precision", choices=["fp32", "mixed"], default="fp32")
+    ap.add_argument("--reorder", choices=["none", "degree"], default="degree",
+                    help="internal renumbering of the articles (set up in fc_create, untimed)")
+    ap.add_argument("--target-iters", type=int, default=100,
+                    help="K of the mixed-precision time-to-target measurement (0 disables it)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-n", type=int, default=1_000_000)
@@ -193,8 +271,8 @@ def main() -> int:
                     help="requests of the serving measurement (0 disables it)")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving measurement and print its JSON line")
-    ap.add_argument("--serve-load", type=float, default=2.0,
-                    help="arrival rate as a multiple of the sequential solve rate")
+    ap.add_argument("--serve-load", default="2.0,0.5",
+                    help="arrival rates as multiples of the sequential solve rate (comma list)")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-timeout", type=float, default=600.0)
@@ -235,13 +313,14 @@ def main() -> int:
     log(f"generating the power-law workload n={args.n:,} c={args.c} on the GPU")
     wl = W.chung_lu_planted(args.n, args.c, 20.0, 2.1, 50_000.0, 0.05, args.seed, device="cuda")
     torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     log(f"generated nnz={wl.nnz:,} (mean degree {wl.meta['realised_mean_deg']:.2f}, max "
         f"{wl.meta['realised_max_deg']:,}) in {time.perf_counter() - t0:.1f} s")
 
     prec = args.precision
     t0 = time.perf_counter()
     solver = fc.Solver(wl.row_ptr, wl.col_idx, wl.val, args.c, wl.U0, precision=prec,
-                       accelerate=True, step=0.0)
+                       accelerate=True, step=0.0, reorder=args.reorder)
     torch.cuda.synchronize()
     log(f"solver created in {time.perf_counter() - t0:.1f} s")
 
@@ -270,7 +349,7 @@ def main() -> int:
     kernels["reduce"] = {"avg_ms": avg["reduce"]}
     kernels["control"] = {"avg_ms": avg["control"]}
     dom = max(("spmm", "fused"), key=lambda k: avg[k])
-    wkey = f"powerlaw_n{n}_c{c}_{prec}"
+    wkey = f"powerlaw_n{n}_c{c}_{prec}_{args.reorder}"
     traffic = measured_traffic(dom, wkey)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["achieved_GBps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -281,10 +360,9 @@ def main() -> int:
     serving = None
     if args.serve_requests > 0:
         serving = serve_bench(args)
-        log(f"serving: {serving['served']['solves_per_s']:.1f} solves/s (p99 "
-            f"{serving['served']['p99_ms']:.1f} ms) vs sequential "
-            f"{serving['sequential_fp32']['solves_per_s']:.1f} solves/s (p99 "
-            f"{serving['sequential_fp32']['p99_ms']:.1f} ms)")
+    mixed_target = None
+    if args.target_iters > 0:
+        mixed_target = mixed_target_bench(args)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, c, n, nnz)
@@ -308,14 +386,15 @@ def main() -> int:
             "workload": (f"power-law fuzzy clustering n={n:,} c={c}: Chung-Lu pattern "
                          f"(exponent 2.1, mean degree 20, max 50,000), {nnz:,} stored nnz, "
                          f"planted communities sigma 0.05, unit diagonal, FISTA constant step "
-                         f"1/L (Theorem 3.1), {prec}"),
-            "n": n, "c": c, "nnz": nnz, "precision": prec, "tau": tau,
+                         f"1/L (Theorem 3.1), {prec}, articles relabelled: {args.reorder}"),
+            "n": n, "c": c, "nnz": nnz, "precision": prec, "reorder": args.reorder, "tau": tau,
             "f0": f0, "f_end": f_end,
         },
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "serving": serving,
+        "mixed_time_to_target": mixed_target,
     }
     print(json.dumps(out), flush=True)
     return 0

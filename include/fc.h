@@ -120,8 +120,23 @@ typedef struct {
     const double *step_schedule; /* host: tau_n for n = 1..step_schedule_len, copied at
                                     fc_create; used by FC_STEP_FIXED when non-NULL */
     int32_t step_schedule_len;
-    int32_t reserved1;
+    int32_t reorder;           /* fc_reorder: FC_REORDER_NONE (default) or
+                                  FC_REORDER_DEGREE, see below */
 } fc_options;
+
+/* Internal numbering of the articles.  FC_REORDER_DEGREE renumbers them by
+ * descending number of stored nonzeros (ties by index) inside fc_create: the
+ * library keeps a permuted copy of S (row_ptr, col_idx and values: 12 bytes
+ * per nonzero in FP32, plus 8 bytes per row) and permutes U0 on the way in
+ * and the iterate on the way out (fc_get_u), so callers see their own order.
+ * Problem (P) is invariant under renumbering the articles, and every row of
+ * the sparse product sums the same terms in the same order; only the order of
+ * the cross-article reductions (share, the loss terms) changes, so results
+ * agree with FC_REORDER_NONE to rounding.  On power-law graphs it places the
+ * rows that most nonzeros gather next to each other, which raises cache reuse
+ * in the sparse product.  Checkpoints record the choice: fc_set_state
+ * rejects a state taken with the other numbering. */
+typedef enum { FC_REORDER_NONE = 0, FC_REORDER_DEGREE = 1 } fc_reorder;
 
 /* Per-solver progress, returned by fc_step and fc_solve. */
 typedef struct {

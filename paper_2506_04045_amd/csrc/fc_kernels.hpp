@@ -235,28 +235,30 @@ __global__ __launch_bounds__(256) void k_reduce_fused_b(const Inst *__restrict__
 // ---------------------------------------------------------------------------
 template <typename Tin, typename Tout>
 __global__ void k_pad_copy(const Tin *__restrict__ src, int64_t ld, Tout *__restrict__ dst,
-                           int64_t rows, int c, int cp) {
+                           int64_t rows, int c, int cp, const int32_t *__restrict__ rowmap) {
     const int64_t total = rows * cp;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx / cp;
         const int k = (int)(idx % cp);
+        const int64_t si = rowmap ? (int64_t)rowmap[i] : i;   // internal row i holds user row si
         Tout v = (Tout)0;
         if (k < c)
-            v = src ? (Tout)src[i * ld + k] : (Tout)(1.0 / c);
+            v = src ? (Tout)src[si * ld + k] : (Tout)(1.0 / c);
         dst[idx] = v;
     }
 }
 
 template <typename Tin, typename Tout>
 __global__ void k_unpad_copy(const Tin *__restrict__ src, int cp, Tout *__restrict__ dst,
-                             int64_t rows, int c) {
+                             int64_t rows, int c, const int32_t *__restrict__ rowmap) {
     const int64_t total = rows * c;
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (int64_t)gridDim.x * blockDim.x) {
         const int64_t i = idx / c;
         const int k = (int)(idx % c);
-        dst[idx] = (Tout)src[i * cp + k];
+        const int64_t si = rowmap ? (int64_t)rowmap[i] : i;   // user row i is internal row si
+        dst[idx] = (Tout)src[si * cp + k];
     }
 }
 
@@ -272,6 +274,74 @@ __global__ void k_convert(const Tin *__restrict__ src, Tout *__restrict__ dst, i
     for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < count;
          idx += (int64_t)gridDim.x * blockDim.x)
         dst[idx] = from_f32<Tout>(to_f32(src[idx]));
+}
+
+// ---------------------------------------------------------------------------
+// Degree relabelling.  The solver may renumber the articles by descending
+// number of stored nonzeros (ties by index): internal row i is user row
+// perm[i], and user row j is internal row inv[j].  The objective and the
+// iteration are equivariant under a simultaneous permutation of S's rows and
+// columns and U's rows, so only locality changes: the rows of U that most
+// nonzeros gather end up side by side.  Each row keeps the order of its
+// nonzeros, so every per-row sum is formed from the same terms in the same
+// order as without relabelling.
+// ---------------------------------------------------------------------------
+__global__ void k_degree_keys(const int64_t *__restrict__ row_ptr, int64_t n,
+                              uint32_t *__restrict__ keys, int32_t *__restrict__ ids) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t d = row_ptr[i + 1] - row_ptr[i];
+        keys[i] = ~(uint32_t)d;   // ascending keys = descending degree
+        ids[i] = (int32_t)i;
+    }
+}
+
+__global__ void k_perm_lengths(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ perm,
+                               int64_t n, int32_t *__restrict__ inv, int64_t *__restrict__ len) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = perm[i];
+        inv[r] = (int32_t)i;
+        len[i] = row_ptr[r + 1] - row_ptr[r];
+    }
+}
+
+// One wave per internal row: copy the user row's nonzeros, renumber their
+// columns, convert their values.
+template <typename VSin, typename VSout>
+__global__ __launch_bounds__(256) void k_permute_csr(const int64_t *__restrict__ row_ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const VSin *__restrict__ val,
+                                                     const int32_t *__restrict__ perm,
+                                                     const int32_t *__restrict__ inv,
+                                                     const int64_t *__restrict__ new_row_ptr, int64_t n,
+                                                     int32_t *__restrict__ new_col,
+                                                     VSout *__restrict__ new_val) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+        const int64_t src = row_ptr[perm[i]];
+        const int64_t dst = new_row_ptr[i], len = new_row_ptr[i + 1] - dst;
+        for (int64_t k = lane; k < len; k += 64) {
+            new_col[dst + k] = inv[col[src + k]];
+            new_val[dst + k] = from_f32<VSout>(to_f32(val[src + k]));
+        }
+    }
+}
+template <>
+__global__ __launch_bounds__(256) void k_permute_csr<double, double>(
+    const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col, const double *__restrict__ val,
+    const int32_t *__restrict__ perm, const int32_t *__restrict__ inv,
+    const int64_t *__restrict__ new_row_ptr, int64_t n, int32_t *__restrict__ new_col,
+    double *__restrict__ new_val) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < n; i += (int64_t)gridDim.x * 4) {
+        const int64_t src = row_ptr[perm[i]];
+        const int64_t dst = new_row_ptr[i], len = new_row_ptr[i + 1] - dst;
+        for (int64_t k = lane; k < len; k += 64) {
+            new_col[dst + k] = inv[col[src + k]];
+            new_val[dst + k] = val[src + k];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------

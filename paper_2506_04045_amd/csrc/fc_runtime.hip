@@ -28,6 +28,9 @@
 #include <thread>
 #include <vector>
 
+#include <hipcub/device/device_radix_sort.hpp>
+#include <hipcub/device/device_scan.hpp>
+
 #include "fc.h"
 #include "fc_kernels.hpp"
 
@@ -381,6 +384,9 @@ struct fc_solver {
     int check_every = 16;
     int max_iter = 100;
     double spec_norm = 0.0, L_thm = 0.0;
+    int reorder = FC_REORDER_NONE;
+    int32_t *d_perm = nullptr;  // internal row i is user row d_perm[i]
+    int32_t *d_inv = nullptr;   // user row j is internal row d_inv[j]
     std::vector<void *> allocs;
     bool pooled = false;  // stream-ordered allocations (serving instances)
     size_t bytes_held = 0;
@@ -648,6 +654,75 @@ namespace {
 
 // Set-up shared by fc_create and the serving engine: `hist_cap` iterations
 // of history, allocations from the stream-ordered pool when `pooled`.
+// Renumber the articles by descending degree (FC_REORDER_DEGREE): a stable
+// radix sort of the complemented row lengths gives perm, then the permuted
+// CSR is written into library-owned arrays with values of type vdt_out.
+fc_status build_degree_order(fc_solver *h, const fc_csr *S, fc_dtype vdt_out, hipStream_t s) {
+    const int64_t n = S->n, nnz = S->nnz;
+    if (n > (int64_t)INT32_MAX)
+        return fail(FC_ERR_UNSUPPORTED, "relabelling needs n < 2^31");
+    int64_t *rp_new = nullptr;
+    int32_t *col_new = nullptr;
+    void *val_new = nullptr;
+    const size_t vbytes = vdt_out == FC_F64 ? 8 : (vdt_out == FC_F32 ? 4 : 2);
+    if (h->alloc(&h->d_perm, sizeof(int32_t) * n) != hipSuccess ||
+        h->alloc(&h->d_inv, sizeof(int32_t) * n) != hipSuccess ||
+        h->alloc(&rp_new, sizeof(int64_t) * (n + 1)) != hipSuccess ||
+        h->alloc(&col_new, sizeof(int32_t) * nnz) != hipSuccess ||
+        h->alloc(&val_new, vbytes * nnz) != hipSuccess)
+        return fail(FC_ERR_OUT_OF_MEMORY, "relabelled copy of S");
+    DevBuf keys, keys_out, ids, len, tmp;
+    if (dev_alloc(keys, sizeof(uint32_t) * n, s) != hipSuccess ||
+        dev_alloc(keys_out, sizeof(uint32_t) * n, s) != hipSuccess ||
+        dev_alloc(ids, sizeof(int32_t) * n, s) != hipSuccess ||
+        dev_alloc(len, sizeof(int64_t) * n, s) != hipSuccess)
+        return fail(FC_ERR_OUT_OF_MEMORY, "relabelling scratch");
+    const int g = grid_1d(n, 256, 16384);
+    hipLaunchKernelGGL(k_degree_keys, dim3(g), dim3(256), 0, s, S->row_ptr, n, (uint32_t *)keys.p,
+                       (int32_t *)ids.p);
+    size_t sort_bytes = 0, scan_bytes = 0;
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t *)keys.p,
+                                              (uint32_t *)keys_out.p, (const int32_t *)ids.p,
+                                              h->d_perm, (int)n, 0, 32, s));
+    HIPCHK(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, (const int64_t *)len.p, rp_new + 1,
+                                            (int)n, s));
+    if (dev_alloc(tmp, std::max(sort_bytes, scan_bytes), s) != hipSuccess)
+        return fail(FC_ERR_OUT_OF_MEMORY, "relabelling scratch");
+    HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp.p, sort_bytes, (const uint32_t *)keys.p,
+                                              (uint32_t *)keys_out.p, (const int32_t *)ids.p,
+                                              h->d_perm, (int)n, 0, 32, s));
+    hipLaunchKernelGGL(k_perm_lengths, dim3(g), dim3(256), 0, s, S->row_ptr, h->d_perm, n, h->d_inv,
+                       (int64_t *)len.p);
+    HIPCHK(hipMemsetAsync(rp_new, 0, sizeof(int64_t), s));
+    HIPCHK(hipcub::DeviceScan::InclusiveSum(tmp.p, scan_bytes, (const int64_t *)len.p, rp_new + 1,
+                                            (int)n, s));
+    const int gw = grid_1d(n, 4, 65536);
+    const bool to_half = vdt_out == FC_F16;
+    if (S->values_dtype == FC_F64)
+        hipLaunchKernelGGL((k_permute_csr<double, double>), dim3(gw), dim3(256), 0, s, S->row_ptr,
+                           S->col_idx, (const double *)S->values, h->d_perm, h->d_inv, rp_new, n, col_new,
+                           (double *)val_new);
+    else if (S->values_dtype == FC_F32 && !to_half)
+        hipLaunchKernelGGL((k_permute_csr<float, float>), dim3(gw), dim3(256), 0, s, S->row_ptr,
+                           S->col_idx, (const float *)S->values, h->d_perm, h->d_inv, rp_new, n, col_new,
+                           (float *)val_new);
+    else if (S->values_dtype == FC_F32)
+        hipLaunchKernelGGL((k_permute_csr<float, __half>), dim3(gw), dim3(256), 0, s, S->row_ptr,
+                           S->col_idx, (const float *)S->values, h->d_perm, h->d_inv, rp_new, n, col_new,
+                           (__half *)val_new);
+    else
+        hipLaunchKernelGGL((k_permute_csr<__half, __half>), dim3(gw), dim3(256), 0, s, S->row_ptr,
+                           S->col_idx, (const __half *)S->values, h->d_perm, h->d_inv, rp_new, n, col_new,
+                           (__half *)val_new);
+    HIPCHK(hipGetLastError());
+    h->row_ptr = rp_new;
+    h->col = col_new;
+    h->val = val_new;
+    h->vdt = vdt_out;
+    h->reorder = FC_REORDER_DEGREE;
+    return FC_OK;
+}
+
 fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc_dtype u0_dtype,
                       hipStream_t stream, int hist_cap, bool pooled, fc_solver **out) {
     if (!out)
@@ -675,6 +750,8 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
         return fail(FC_ERR_INVALID_ARG, "step_schedule_len must be >= 1");
     if (opt->norm_estimate != 0 && opt->norm_estimate != 1)
         return fail(FC_ERR_INVALID_ARG, "norm_estimate must be 0 or 1");
+    if (opt->reorder != FC_REORDER_NONE && opt->reorder != FC_REORDER_DEGREE)
+        return fail(FC_ERR_INVALID_ARG, "unknown reorder mode");
     if (U0 && u0_dtype != FC_F64 && u0_dtype != FC_F32)
         return fail(FC_ERR_INVALID_ARG, "U0 must be FC_F64 or FC_F32");
     if (opt->precision == FC_PREC_FP64 && S->values_dtype != FC_F64)
@@ -755,7 +832,12 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
             h->alloc(&h->shadow[k], (size_t)h->n * h->cp * 2) != hipSuccess)
             return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "bfloat16 shadow buffers"));
     }
-    if (h->prec == FC_PREC_MIXED && S->values_dtype == FC_F32) {
+    if (opt->reorder == FC_REORDER_DEGREE) {
+        const fc_dtype vout = h->prec == FC_PREC_MIXED ? FC_F16 : S->values_dtype;
+        st = build_degree_order(h, S, vout, s);
+        if (st != FC_OK)
+            return cleanup(st);
+    } else if (h->prec == FC_PREC_MIXED && S->values_dtype == FC_F32) {
         if (h->alloc(&h->val_owned, (size_t)S->nnz * 2) != hipSuccess)
             return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "half copy of S"));
         hipLaunchKernelGGL((k_convert<float, __half>), dim3(grid_1d(S->nnz, 256, 8192)), dim3(256), 0, s,
@@ -786,7 +868,7 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
         });
         h->g_spmm = grid_1d(h->n, rows_per_wg, (int64_t)cus * 32);
     }
-    st = build_heavy_plan(S->row_ptr, S->n, h->prec == FC_PREC_FP64 ? 8 : 4, h->cp, s, h->heavy);
+    st = build_heavy_plan(h->row_ptr, S->n, h->prec == FC_PREC_FP64 ? 8 : 4, h->cp, s, h->heavy);
     if (st != FC_OK)
         return cleanup(st);
     h->g_comb = combine_grid(h->heavy.nheavy, 256 / h->cp);
@@ -853,17 +935,21 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
         if (h->prec == FC_PREC_FP64) {
             if (!U0 || u0_dtype == FC_F64)
                 hipLaunchKernelGGL((k_pad_copy<double, double>), dim3(g), dim3(256), 0, s,
-                                   (const double *)U0, (int64_t)h->c, (double *)h->X[k], h->n, h->c, h->cp);
+                                   (const double *)U0, (int64_t)h->c, (double *)h->X[k], h->n, h->c, h->cp,
+                                   (const int32_t *)h->d_perm);
             else
                 hipLaunchKernelGGL((k_pad_copy<float, double>), dim3(g), dim3(256), 0, s,
-                                   (const float *)U0, (int64_t)h->c, (double *)h->X[k], h->n, h->c, h->cp);
+                                   (const float *)U0, (int64_t)h->c, (double *)h->X[k], h->n, h->c, h->cp,
+                                   (const int32_t *)h->d_perm);
         } else {
             if (!U0 || u0_dtype == FC_F32)
                 hipLaunchKernelGGL((k_pad_copy<float, float>), dim3(g), dim3(256), 0, s,
-                                   (const float *)U0, (int64_t)h->c, (float *)h->X[k], h->n, h->c, h->cp);
+                                   (const float *)U0, (int64_t)h->c, (float *)h->X[k], h->n, h->c, h->cp,
+                                   (const int32_t *)h->d_perm);
             else
                 hipLaunchKernelGGL((k_pad_copy<double, float>), dim3(g), dim3(256), 0, s,
-                                   (const double *)U0, (int64_t)h->c, (float *)h->X[k], h->n, h->c, h->cp);
+                                   (const double *)U0, (int64_t)h->c, (float *)h->X[k], h->n, h->c, h->cp,
+                                   (const int32_t *)h->d_perm);
         }
         if (hipMemsetAsync(h->Z[k], 0, mat_bytes, s) != hipSuccess)
             return cleanup(fail(FC_ERR_DEVICE, "memset"));
@@ -874,6 +960,8 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
     // ||S_eff||_F^2 and the step bound of Theorem 3.1
     double s2 = 0.0;
     fc_csr Sv = *S;
+    Sv.row_ptr = h->row_ptr;
+    Sv.col_idx = h->col;
     Sv.values = h->val;
     Sv.values_dtype = h->vdt;
     st = sum_squares(&Sv, s, &s2);
@@ -1007,17 +1095,17 @@ fc_status fc_get_u(const fc_solver *h, void *U_out, fc_dtype dtype) {
     if (h->prec == FC_PREC_FP64) {
         if (dtype == FC_F64)
             hipLaunchKernelGGL((k_unpad_copy<double, double>), dim3(g), dim3(256), 0, s,
-                               (const double *)src, h->cp, (double *)U_out, h->n, h->c);
+                               (const double *)src, h->cp, (double *)U_out, h->n, h->c, (const int32_t *)h->d_inv);
         else
             hipLaunchKernelGGL((k_unpad_copy<double, float>), dim3(g), dim3(256), 0, s,
-                               (const double *)src, h->cp, (float *)U_out, h->n, h->c);
+                               (const double *)src, h->cp, (float *)U_out, h->n, h->c, (const int32_t *)h->d_inv);
     } else {
         if (dtype == FC_F64)
             hipLaunchKernelGGL((k_unpad_copy<float, double>), dim3(g), dim3(256), 0, s,
-                               (const float *)src, h->cp, (double *)U_out, h->n, h->c);
+                               (const float *)src, h->cp, (double *)U_out, h->n, h->c, (const int32_t *)h->d_inv);
         else
             hipLaunchKernelGGL((k_unpad_copy<float, float>), dim3(g), dim3(256), 0, s,
-                               (const float *)src, h->cp, (float *)U_out, h->n, h->c);
+                               (const float *)src, h->cp, (float *)U_out, h->n, h->c, (const int32_t *)h->d_inv);
     }
     HIPCHK(hipGetLastError());
     return FC_OK;
@@ -1068,7 +1156,7 @@ struct CkptHeader {
     uint32_t header_bytes;
     int64_t n;
     int32_t c, cp, prec, accelerate, backtrack, diag;
-    int32_t hist_len, reserved;
+    int32_t hist_len, reorder;
     DevState st;
 };
 constexpr uint64_t CKPT_MAGIC = 0x3130545043434646ull;  // "FFCCPT01"
@@ -1110,6 +1198,7 @@ fc_status fc_get_state(const fc_solver *h, void *buf, size_t *bytes) {
     hd.accelerate = h->accelerate;
     hd.backtrack = h->backtrack;
     hd.diag = (int32_t)h->diag;
+    hd.reorder = h->reorder;
     hd.hist_len = hist_len;
     hd.st = h->h;
     char *p = (char *)buf;
@@ -1148,7 +1237,8 @@ fc_status fc_set_state(fc_solver *h, const void *buf, size_t bytes) {
     if (hd.magic != CKPT_MAGIC || hd.version != 1 || hd.header_bytes != sizeof(CkptHeader))
         return fail(FC_ERR_INVALID_ARG, "not a checkpoint of this library version");
     if (hd.n != h->n || hd.c != h->c || hd.cp != h->cp || hd.prec != (int32_t)h->prec ||
-        hd.accelerate != h->accelerate || hd.backtrack != h->backtrack || hd.diag != (int32_t)h->diag)
+        hd.accelerate != h->accelerate || hd.backtrack != h->backtrack || hd.diag != (int32_t)h->diag ||
+        hd.reorder != h->reorder)
         return fail(FC_ERR_INVALID_ARG, "checkpoint was taken from a solver with other n, c or options");
     if (hd.hist_len < 1 || hd.hist_len > h->hist_cap || bytes < ckpt_bytes(h, hd.hist_len))
         return fail(FC_ERR_INVALID_ARG, "checkpoint buffer truncated");
@@ -1260,10 +1350,10 @@ fc_status pad_user(const void *U, fc_dtype dt, int64_t n, int c, int cp, T *dst,
     const int g = grid_1d(n * cp, 256, 8192);
     if (dt == FC_F64)
         hipLaunchKernelGGL((k_pad_copy<double, T>), dim3(g), dim3(256), 0, s, (const double *)U,
-                           (int64_t)c, dst, n, c, cp);
+                           (int64_t)c, dst, n, c, cp, (const int32_t *)nullptr);
     else
         hipLaunchKernelGGL((k_pad_copy<float, T>), dim3(g), dim3(256), 0, s, (const float *)U,
-                           (int64_t)c, dst, n, c, cp);
+                           (int64_t)c, dst, n, c, cp, (const int32_t *)nullptr);
     HIPCHK(hipGetLastError());
     return FC_OK;
 }
@@ -1305,7 +1395,8 @@ fc_status fc_spmm(const fc_csr *S, fc_diag diag, const void *U, void *Z, fc_dtyp
             if (r != FC_OK)
                 return r;
             hipLaunchKernelGGL((k_unpad_copy<double, double>), dim3(g), dim3(256), 0, s,
-                               (const double *)zp.p, CP, (double *)Z, S->n, c);
+                               (const double *)zp.p, CP, (double *)Z, S->n, c,
+                               (const int32_t *)nullptr);
         } else {
             r = pad_user<float>(U, dtype, S->n, c, CP, (float *)up.p, s);
             if (r != FC_OK)
@@ -1319,7 +1410,8 @@ fc_status fc_spmm(const fc_csr *S, fc_diag diag, const void *U, void *Z, fc_dtyp
             if (r != FC_OK)
                 return r;
             hipLaunchKernelGGL((k_unpad_copy<float, float>), dim3(g), dim3(256), 0, s,
-                               (const float *)zp.p, CP, (float *)Z, S->n, c);
+                               (const float *)zp.p, CP, (float *)Z, S->n, c,
+                               (const int32_t *)nullptr);
         }
         HIPCHK(hipGetLastError());
         return FC_OK;

@@ -1,0 +1,127 @@
+"""Parity at the full benchmark sizes, on sampled articles.
+
+Workloads: the power-law instance (n = 70,000,000, c = 32, Chung-Lu pattern
+of mean degree 20, about 1.4e9 stored nonzeros, FP32) in the launch
+configuration the benchmark times, and the ER instance of average degree 30
+at the same n (about 2.1e9 stored nonzeros) in mixed precision.
+
+The FP64 oracle cannot run whole iterations at this size in seconds, so it
+evaluates, at a sample of articles (random ones plus the highest-degree hubs
+and rows of every length class), the products X s_i of the seeded start and
+one projected gradient step from it (Alg. 2; the first FISTA step of Alg. 4,
+whose inertial term is zero), with share = X X^T over all N articles.  Every
+oracle input is the seeded workload and a fixed step.  Later iterations are
+covered by properties that hold at any size: columns on the simplex and
+bitwise-identical reruns.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+
+pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
+
+TAU = 1.0e-9          # fixed step, below 1/L_thm (about 1.19e-9) at n = 7e7
+
+
+@pytest.fixture(scope="module")
+def fc():
+    import paper_2506_04045_amd as fc
+    fc.library_path()
+    return fc
+
+
+def _sample(row_ptr, seed, k=2000):
+    """Random articles plus the 8 largest rows and rows of each length class
+    (at most 64, 65-2,048, more than 2,048 nonzeros); sorted, distinct."""
+    deg = (row_ptr[1:] - row_ptr[:-1]).cpu().numpy()
+    rng = np.random.default_rng(seed)
+    rows = [rng.integers(0, deg.shape[0], k), np.argsort(deg)[-8:]]
+    for lo, hi in ((0, 0), (1, 64), (65, 2048), (2049, 1 << 40)):
+        cand = np.flatnonzero((deg >= lo) & (deg <= hi))
+        if cand.size:
+            rows.append(rng.choice(cand, min(64, cand.size), replace=False))
+    return np.unique(np.concatenate(rows)).astype(np.int64)
+
+
+def _sub_csr(row_ptr, col_idx, val, rows):
+    """Rows `rows` of the device CSR, copied to the host."""
+    r = torch.from_numpy(rows).to(row_ptr.device)
+    beg, lens = row_ptr[r], row_ptr[r + 1] - row_ptr[r]
+    sub_rp = torch.zeros(rows.shape[0] + 1, dtype=torch.int64, device=row_ptr.device)
+    torch.cumsum(lens, 0, out=sub_rp[1:])
+    total = int(sub_rp[-1])
+    owner = torch.repeat_interleave(torch.arange(rows.shape[0], device=row_ptr.device), lens)
+    idx = beg[owner] + (torch.arange(total, device=row_ptr.device) - sub_rp[owner])
+    return (sub_rp.cpu().numpy(), col_idx[idx].cpu().numpy(),
+            val[idx].double().cpu().numpy())
+
+
+def _check_first_step(fc, wl, precision, val_for_oracle, seed, reorders=("degree",)):
+    rows = _sample(wl.row_ptr, seed)
+    sub_rp, sub_ci, sub_v = _sub_csr(wl.row_ptr, wl.col_idx, wl.val, rows)
+    if val_for_oracle is not None:
+        sub_v = val_for_oracle(sub_v)
+    U0 = wl.U0.cpu().numpy().astype(np.float64)
+
+    # sparse product of the start at the sampled articles
+    if precision == "fp32":
+        Z = fc.spmm(wl.row_ptr, wl.col_idx, wl.val, wl.U0)
+        z_gpu = Z[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+        del Z
+        torch.cuda.empty_cache()
+        z_ref = oracle.x_s_rows(rows, sub_rp, sub_ci, sub_v, True, U0)
+        err = np.linalg.norm(z_gpu - z_ref) / np.linalg.norm(z_ref)
+        print(f"full-size product, {rows.size} sampled rows: normwise {err:.2e}")
+        assert err <= 1e-5
+
+    # one step in the benchmark's launch configuration (articles relabelled by
+    # degree inside the solver), and without relabelling
+    x_ref = oracle.step_rows(rows, sub_rp, sub_ci, sub_v, True, U0, TAU)
+    moved = np.abs(x_ref - U0[rows]).max()
+    for reorder in reorders:
+        with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, precision=precision,
+                       accelerate=True, step=TAU, reorder=reorder) as s:
+            s.step(1)
+            U1 = s.get_u()
+            x_gpu = U1[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+            del U1
+        du = np.abs(x_gpu - x_ref).max()
+        print(f"full-size first step ({precision}, relabelling {reorder}), {rows.size} sampled "
+              f"rows: max|dU| {du:.2e} (the step moves entries by up to {moved:.2e})")
+        # FP32 iterates of magnitude <= 1 carry ulps of at most 6e-8; the
+        # step itself moves entries by about 4 tau n u_k / (c (c + 1)) ~ 1e-5
+        assert du <= (1e-7 if precision == "fp32" else 5e-7)
+        assert moved > 20 * du
+
+
+def test_power_law_full_size_fp32(fc):
+    wl = W.config_full_power_law(device="cuda")
+    torch.cuda.synchronize()
+    _check_first_step(fc, wl, "fp32", None, seed=1, reorders=("degree", "none"))
+
+    # later iterations: simplex columns and bitwise-identical reruns
+    def run(k):
+        with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, accelerate=True,
+                       step=0.0, reorder="degree") as s:
+            info = s.step(k)
+            return info, s.get_u()
+    info_a, Ua = run(12)
+    assert (Ua >= 0).all()
+    assert float((Ua.double().sum(1) - 1).abs().max()) <= 1e-5
+    info_b, Ub = run(12)
+    assert info_a.f == info_b.f and torch.equal(Ua, Ub)
+    del Ua, Ub, wl
+    torch.cuda.empty_cache()
+
+
+def test_er_degree_30_full_size_mixed(fc):
+    wl = W.config_mixed_full(device="cuda")
+    torch.cuda.synchronize()
+    assert wl.nnz > 2_000_000_000
+    fp16 = lambda v: v.astype(np.float32).astype(np.float16).astype(np.float64)
+    _check_first_step(fc, wl, "mixed", fp16, seed=2)
+    del wl
+    torch.cuda.empty_cache()

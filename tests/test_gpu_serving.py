@@ -150,3 +150,12 @@ def test_a_served_solve_follows_the_oracle(fc):
     assert r.iter == 40
     assert abs(r.f - ref.f[-1]) <= 1e-4 * abs(ref.f[-1])
     assert np.abs(U - ref.X).max() <= 1e-4
+
+
+def test_relabelled_requests_match_their_solo_runs(fc):
+    reqs = _requests(6, seed0=1100)
+    alone = [_alone(fc, wl, reorder="degree") for wl in reqs]
+    served = _serve(fc, reqs, dict(ticks_per_poll=2), reorder="degree")
+    for i in range(len(reqs)):
+        r, U = served[i]
+        assert r.status == 0 and r.f == alone[i][0].f and np.array_equal(U, alone[i][1])

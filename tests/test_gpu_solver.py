@@ -317,3 +317,67 @@ def test_power_law_instance_follows_the_oracle(fc, prec):
           f"max|dU|={np.abs(U - ref.X).max():.2e}")
     assert np.abs(U - ref.X).max() <= tol
     assert abs(info.f - ref.f[-1]) <= tol * abs(ref.f[-1])
+
+
+# --------------------------------------------------------------------------
+# degree relabelling (internal renumbering of the articles)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_degree_relabelling_follows_the_oracle(fc, prec):
+    """With the articles renumbered by degree inside the solver, the iterate
+    handed back (in the caller's order) still follows the oracle run on the
+    caller's numbering, and agrees with the solver run without renumbering."""
+    wl = W.chung_lu_planted(20000, 16, 20.0, 2.1, 50_000.0, 0.05, 7,
+                            val_dtype=torch.float64, u_dtype=torch.float64)
+    rp, ci, v, U0 = wl.numpy()
+    if prec != "fp64":
+        v = v.astype(np.float32).astype(np.float64)
+        U0 = U0.astype(np.float32).astype(np.float64)
+    v_ref = v.astype(np.float16).astype(np.float64) if prec == "mixed" else v
+    spec, _ = oracle.spectral_norm(rp, ci, v_ref, True)
+    tau = 20.0 / oracle.lipschitz_bound(spec, wl.n)
+    ref = oracle.solve(rp, ci, v_ref, True, U0, accelerate=True, max_iter=40, step=tau)
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, 16, prec, 40, step=tau, reorder="degree")
+    info0, U_plain, _ = _solve_gpu(fc, rp, ci, v, U0, 16, prec, 40, step=tau)
+    tol = {"fp64": 1e-9, "fp32": 1e-4, "mixed": 5e-3}[prec]
+    du = np.abs(U - ref.X).max()
+    print(f"relabelled {prec}: f_rel={abs(info.f - ref.f[-1]) / abs(ref.f[-1]):.2e} "
+          f"max|dU|={du:.2e} max|dU| vs unrelabelled={np.abs(U - U_plain).max():.2e}")
+    assert du <= tol
+    assert abs(info.f - ref.f[-1]) <= (1e-9 if prec == "fp64" else 1e-4) * abs(ref.f[-1])
+    assert np.abs(U - U_plain).max() <= {"fp64": 1e-12, "fp32": 1e-5, "mixed": 1e-3}[prec]
+    assert np.abs(U.sum(1) - 1).max() <= 1e-6
+
+
+def test_degree_relabelling_checkpoints(fc):
+    wl = W.chung_lu_planted(6000, 8, 20.0, 2.1, 5_000.0, 0.05, 8).to("cuda")
+    kw = dict(step=1e-4, reorder="degree")
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 8, wl.U0, **kw) as a:
+        a.step(20)
+        U_ref, f_ref = a.get_u().cpu().numpy(), a.info().f
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 8, wl.U0, **kw) as b:
+        b.step(9)
+        state = b.get_state()
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 8, None, **kw) as c:
+        c.set_state(state)
+        c.step(11)
+        assert np.array_equal(c.get_u().cpu().numpy(), U_ref) and c.info().f == f_ref
+    from paper_2506_04045_amd import _native
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 8, None, step=1e-4) as d:
+        with pytest.raises(_native.FcError):
+            d.set_state(state)
+
+
+def test_degree_relabelling_with_hub_rows_and_empty_rows(fc):
+    from tests.gpu_util import star_plus_er
+    rp, ci, v = star_plus_er(6000, 3.0, 21, hub_frac=0.9)
+    deg = np.diff(rp)
+    assert deg.max() > 2 * 2048 and (deg == 0).any()
+    n, c = 6000, 8
+    U0 = pins.random_simplex_rows(n, c, np.random.default_rng(21))
+    ref = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=20, step=2e-4)
+    info, U, _ = _solve_gpu(fc, rp, ci, v, U0, c, "fp64", 20, step=2e-4, reorder="degree",
+                            validate=True)
+    assert np.abs(U - ref.X).max() <= 1e-9
+    assert abs(info.f - ref.f[-1]) <= 1e-9 * abs(ref.f[-1])
