@@ -284,11 +284,17 @@ def main() -> int:
         import torch
         x = torch.ones(args.calibrate_copy_mb * (1 << 18), device="cuda")
         y = torch.empty_like(x)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        torch.mul(x, 1.0, out=y)
+        ev[0].record()
         for _ in range(5):
             torch.mul(x, 1.0, out=y)
+        ev[1].record()
         torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / 5
         print(json.dumps({"calibration": "elementwise copy", "bytes_read_per_launch": x.numel() * 4,
-                          "bytes_written_per_launch": y.numel() * 4, "launches": 5}))
+                          "bytes_written_per_launch": y.numel() * 4, "launches": 6,
+                          "ms_per_launch": ms, "GBps": 2 * x.numel() * 4 / (ms * 1e6)}))
         return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))

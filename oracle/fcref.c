@@ -328,6 +328,15 @@ enum { FCREF_STOP_MAXITER = 0, FCREF_STOP_LOSS = 1, FCREF_STOP_PGRAD = 2,
  * Logs (each may be NULL): f_log[0..it], tau_log[1..it], trials_log[1..it],
  * r_log[1..it].  Returns the number of completed iterations; X_out receives
  * the output Xbar of the last completed iteration.
+ *
+ * Parity unpinned (inertial trajectory): the paper prints no value of an
+ * accelerated run, so the inertial sequence is checked only through what
+ * fixes it otherwise -- with the inertial term dropped it is the GPA of
+ * Example 4.1 and Theorem 3.1 (pinned); a planted exact factorisation is a
+ * fixed point; the first two steps coincide with GPA (beta_1 = 0) and the
+ * third differs; and an independent dense re-implementation agrees.  The
+ * backtracking rule is not in the paper either: it is checked by its
+ * acceptance test and the minimality of the accepted L.
  */
 int fcref_solve(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
                 const double *val, int diag_unit, int C, const double *X0,

@@ -35,25 +35,25 @@ template <typename T> struct Acc4;
 template <> struct Acc4<float> { typedef floatx4 type; };
 template <> struct Acc4<double> { typedef doublex4 type; };
 
-// 16x16x4 matrix-core product, D = A B + C.  Operand layout for lane l:
-// A[l % 16][l / 16], B[l / 16][l % 16]; result register q of lane l holds
-// D[4 (l / 16) + q][l % 16].
+// 16x16x4 matrix-core products, D = A B + C, operand layout for lane l:
+// A[l % 16][l / 16], B[l / 16][l % 16].  The result registers differ between
+// the two types: register q of lane l holds D[4 (l / 16) + q][l % 16] for
+// FP32 and D[4 q + l / 16][l % 16] for FP64 (mfma_row gives the row).
 __device__ __forceinline__ floatx4 mfma16x16x4(float a, float b, floatx4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
-// The double version keeps the same lane contract, computed with cross-lane
-// reads and FP64 FMAs: lane (r, g) needs A[4g+q][k] (held by lane 16k+4g+q)
-// and B[k][r] (held by lane 16k+r).  It is used by the FP64 solver only.
 __device__ __forceinline__ doublex4 mfma16x16x4(double a, double b, doublex4 c) {
-    const int l = threadIdx.x & 63, r = l & 15, g = l >> 4;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const double bk = __shfl(b, 16 * k + r, 64);
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            c[q] = fma(__shfl(a, 16 * k + 4 * g + q, 64), bk, c[q]);
-    }
-    return c;
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <typename T> __device__ __forceinline__ int mfma_row(int g, int q) { return 4 * g + q; }
+template <> __device__ __forceinline__ int mfma_row<double>(int g, int q) { return 4 * q + g; }
+
+// Component of a row held in slot s by lane group g in the fused kernel.
+// The layout is chosen so that the Y G product comes back from the matrix
+// cores in the registers that hold y: slot s = 4a + q of lane group g is
+// component 16a + mfma_row(g, q).
+template <typename T> __device__ __forceinline__ int kslot(int s, int g) {
+    return 16 * (s >> 2) + mfma_row<T>(g, s & 3);
 }
 
 template <typename T> __device__ __forceinline__ float to_f32(T v) { return (float)v; }
@@ -575,6 +575,9 @@ __device__ __forceinline__ void team_slot_sum(TA (&acc)[NE]) {
 
 // Row epilogue of a team whose slots are already summed: slot 0 adds u_i for
 // the unit diagonal, writes z_i and returns <u_i, z_i> on its sub-0 lane.
+// u_i and z_i are touched once per launch, so they go through the caches as
+// non-temporal accesses and leave room for the gathered rows (measured 3 %
+// faster at n = 7e7).
 template <int GS, typename TA, typename TZ, typename TX, int CP, int NE>
 __device__ __forceinline__ double row_epilogue(bool live, int slot, int sub, int64_t row,
                                                const TX *__restrict__ X, TZ *__restrict__ Z,
@@ -584,14 +587,14 @@ __device__ __forceinline__ double row_epilogue(bool live, int slot, int sub, int
         TA xi[NE];
 #pragma unroll
         for (int q = 0; q < NE; ++q)
-            xi[q] = (TA)X[row * CP + sub * NE + q];
+            xi[q] = (TA)__builtin_nontemporal_load(&X[row * CP + sub * NE + q]);
         if (diag_unit)
 #pragma unroll
             for (int q = 0; q < NE; ++q)
                 acc[q] += xi[q];
 #pragma unroll
         for (int q = 0; q < NE; ++q) {
-            Z[row * CP + sub * NE + q] = (TZ)acc[q];
+            __builtin_nontemporal_store((TZ)acc[q], &Z[row * CP + sub * NE + q]);
             d += (double)acc[q] * (double)xi[q];
         }
     }
@@ -845,7 +848,7 @@ __global__ __launch_bounds__(256) void k_gram(const T *__restrict__ X, int64_t n
         SymBlocks<M>::ab(kb, a, b);
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            const int i = 16 * a + 4 * g + q, j = 16 * b + r;
+            const int i = 16 * a + mfma_row<T>(g, q), j = 16 * b + r;
             out[i * CPM + j] = acc64[kb][q];
             if (a != b)
                 out[j * CPM + i] = acc64[kb][q];
@@ -915,6 +918,8 @@ __device__ __forceinline__ double simplex_threshold(const T (&v)[NC], const bool
 // p + y, p - y when backtracking) in LDS and each wave accumulates some of
 // the 16 x 16 blocks of their Gram matrices on the matrix cores.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t nwt_of(int64_t n) { return (n + 63) / 64; }
+
 template <typename T, int CP, bool ACCEL, bool BT, bool SHADOW>
 __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t nblk) {
     constexpr int CPM = CP < 16 ? 16 : CP;
@@ -958,7 +963,7 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
     for (int a = 0; a < M; ++a)
 #pragma unroll
         for (int s = 0; s < NC; ++s)
-            gA[a][s] = GYs[(16 * a + r) * CPM + 16 * (s >> 2) + 4 * g + (s & 3)];
+            gA[a][s] = GYs[(16 * a + r) * CPM + kslot<T>(s, g)];
 
     __shared__ T lds[NMAT][64 * STRIDE];
 
@@ -968,11 +973,11 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
     for (int k = 0; k < BPW; ++k)
         acc64[k] = doublex4{0, 0, 0, 0};
 
-    const int64_t nwt = (n + 63) / 64;
-    for (int64_t wt = blk; wt < nwt; wt += nblk) {
+    // The four row streams of one 64-row tile (loading the next tile ahead of
+    // the arithmetic was measured slower: the extra registers cost occupancy).
+    auto load_tile = [&](int64_t wt, T (&xc)[NC], T (&zc)[NC], T (&xp)[NC], T (&zp)[NC]) {
         const int64_t row = wt * 64 + wave * 16 + r;
-        const bool live = row < n;
-        T xc[NC], xp[NC], zc[NC], zp[NC];
+        const bool live = wt < nwt_of(n) && row < n;
 #pragma unroll
         for (int a = 0; a < M; ++a) {
             const int k0 = 16 * a + 4 * g;
@@ -984,7 +989,7 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
                 xp[4 * a + q] = (T)0;
                 zp[4 * a + q] = (T)0;
             }
-            if (ok) {
+            if (ok && sizeof(T) == 4) {   // four consecutive components
                 T t4[4];
                 GatherLoad<T, 4>::load(Xc + row * CP + k0, t4);
 #pragma unroll
@@ -1004,8 +1009,28 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
                     for (int q = 0; q < 4; ++q)
                         zp[4 * a + q] = t4[q];
                 }
+            } else if (live && sizeof(T) == 8) {   // components 16a + 4q + g
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int k = kslot<T>(4 * a + q, g);
+                    if (k < CP) {
+                        xc[4 * a + q] = Xc[row * CP + k];
+                        zc[4 * a + q] = Zc[row * CP + k];
+                        if (use_prev) {
+                            xp[4 * a + q] = Xp[row * CP + k];
+                            zp[4 * a + q] = Zp[row * CP + k];
+                        }
+                    }
+                }
             }
         }
+    };
+    const int64_t nwt = nwt_of(n);
+    for (int64_t wt = blk; wt < nwt; wt += nblk) {
+        const int64_t row = wt * 64 + wave * 16 + r;
+        const bool live = row < n;
+        T xc[NC], xp[NC], zc[NC], zp[NC];
+        load_tile(wt, xc, zc, xp, zp);
         T y[NC], sy[NC];
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
@@ -1028,7 +1053,7 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
         bool valid[NC];
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
-            const int k = 16 * (s >> 2) + 4 * g + (s & 3);
+            const int k = kslot<T>(s, g);
             valid[s] = live && k < c;
             grad[s] = (T)(-4) * (sy[s] - yg[s]);
             v[s] = y[s] - tau * grad[s];
@@ -1064,15 +1089,14 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
         // new iterate (and its bfloat16 copy for the next sparse product)
 #pragma unroll
         for (int a = 0; a < M; ++a) {
-            const int k0 = 16 * a + 4 * g;
-            if (live && k0 < CP) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
-                    Xn[row * CP + k0 + q] = p[4 * a + q];
-                if (SHADOW)
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        shadow[row * CP + k0 + q] = __float2bfloat16((float)p[4 * a + q]);
+            for (int q = 0; q < 4; ++q) {
+                const int k = kslot<T>(4 * a + q, g);
+                if (live && k < CP) {
+                    Xn[row * CP + k] = p[4 * a + q];
+                    if (SHADOW)
+                        shadow[row * CP + k] = __float2bfloat16((float)p[4 * a + q]);
+                }
             }
         }
         // stage the tile for the Gram products
@@ -1080,7 +1104,7 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
         const int lrow = wave * 16 + r;
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
-            const int k = 16 * (s >> 2) + 4 * g + (s & 3);
+            const int k = kslot<T>(s, g);
             lds[0][lrow * STRIDE + k] = p[s];
             if constexpr (ACCEL)
                 lds[1][lrow * STRIDE + k] = bn1 * p[s] - bn0 * xc[s];
@@ -1144,7 +1168,7 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
             double *o = out + mat * L::MAT;
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const int i = 16 * a + 4 * g + q, j = 16 * b + r;
+                const int i = 16 * a + mfma_row<T>(g, q), j = 16 * b + r;
                 o[i * CPM + j] = acc64[kk][q];
                 if (sym && a != b)
                     o[j * CPM + i] = acc64[kk][q];

@@ -866,7 +866,7 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
                 rows_per_wg = SpmmCfg<__hip_bfloat16, CP>::ROWS_PER_WG;
             return FC_OK;
         });
-        h->g_spmm = grid_1d(h->n, rows_per_wg, (int64_t)cus * 32);
+        h->g_spmm = grid_1d(h->n, rows_per_wg, (int64_t)cus * 64);
     }
     st = build_heavy_plan(h->row_ptr, S->n, h->prec == FC_PREC_FP64 ? 8 : 4, h->cp, s, h->heavy);
     if (st != FC_OK)
@@ -1313,7 +1313,7 @@ fc_status spmm_and_gram_t(const fc_csr *S, fc_diag diag, const T *Upad, T *Zpad,
     I.c = CP;
     I.diag_unit = diag == FC_DIAG_UNIT ? 1 : 0;
     plan_to_inst(hp, I);
-    I.g_spmm = grid_1d(n, Cfg::ROWS_PER_WG, (int64_t)cus * 32);
+    I.g_spmm = grid_1d(n, Cfg::ROWS_PER_WG, (int64_t)cus * 64);
     I.g_comb = combine_grid(hp.nheavy, 256 / CP);
     I.X[0] = (void *)Upad;
     I.Z[0] = Zpad;

@@ -55,3 +55,30 @@ def test_mixed_against_fp64_oracle(fc, c):
     assert np.abs(U.sum(1) - 1).max() <= 1e-6
     assert (U >= 0).all()
     assert du16 <= 5e-3
+
+
+def test_mixed_on_the_medium_config_twin(fc):
+    """The n = 1e6, c = 32 instance (ER degree 30): mixed precision against
+    the oracle on S and on S rounded to FP16, 10 iterations."""
+    wl = W.config_medium(seed=0)
+    rp, ci, v, U0 = wl.numpy()
+    v32 = v.astype(np.float32)
+    v16 = v32.astype(np.float16).astype(np.float64)
+    tau = 20.0 / oracle.lipschitz_bound(np.sqrt((v16 ** 2).sum() + wl.n), wl.n)
+    iters = 10
+    ref16 = oracle.solve(rp, ci, v16, True, U0, accelerate=True, max_iter=iters, step=tau)
+    ref = oracle.solve(rp, ci, v32.astype(np.float64), True, U0, accelerate=True,
+                       max_iter=iters, step=tau)
+    S = csr_to_dev(rp, ci, v32, torch.float32)
+    with fc.Solver(*S, 32, dev(U0.astype(np.float32)), precision="mixed", step=tau,
+                   reorder="degree") as s:
+        info = s.step(iters)
+        U = s.get_u(torch.float64).cpu().numpy()
+    f_rel16 = abs(info.f - ref16.f[-1]) / abs(ref16.f[-1])
+    f_rel = abs(info.f - ref.f[-1]) / abs(ref.f[-1])
+    du16, du = np.abs(U - ref16.X).max(), np.abs(U - ref.X).max()
+    print(f"mixed medium: f_rel(fp16 S)={f_rel16:.2e} f_rel(S)={f_rel:.2e} "
+          f"max|dU|(fp16 S)={du16:.2e} max|dU|(S)={du:.2e}")
+    assert f_rel16 <= 1e-4
+    assert np.abs(U.sum(1) - 1).max() <= 1e-6 and (U >= 0).all()
+    assert du16 <= 5e-3

@@ -381,3 +381,23 @@ def test_degree_relabelling_with_hub_rows_and_empty_rows(fc):
                             validate=True)
     assert np.abs(U - ref.X).max() <= 1e-9
     assert abs(info.f - ref.f[-1]) <= 1e-9 * abs(ref.f[-1])
+
+
+def test_medium_config_replays_backtracking_fp32(fc):
+    """The n = 1e6, c = 32 configuration (ER degree 30, 3e7 nonzeros):
+    backtracking FISTA in the oracle, its accepted steps replayed by the FP32
+    solver (a few iterations: the oracle takes about a second per trial)."""
+    wl = W.config_medium(seed=0)
+    rp, ci, v, U0 = wl.numpy()
+    assert wl.nnz > 29_000_000
+    ref = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=6, backtrack=True,
+                       L0=1e4)
+    assert ref.trials[1:].sum() > 6          # at least one rejected trial
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, 32, "fp32", 6, step_schedule=ref.tau[1:])
+    f_rel = abs(info.f - ref.f[-1]) / abs(ref.f[-1])
+    df = ref.f[0] - ref.f[-1]
+    df_rel = abs((hist["f"][0] - info.f) - df) / abs(df)
+    du = np.abs(U - ref.X).max()
+    print(f"medium replay fp32: f_rel={f_rel:.2e} df_rel={df_rel:.2e} max|dU|={du:.2e}")
+    assert f_rel <= 1e-4 and df_rel <= 1e-3 and du <= 1e-4
+    assert np.abs(U.sum(1) - 1).max() <= 1e-6
