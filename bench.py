@@ -133,7 +133,8 @@ def serve_bench(args) -> dict:
         f_seq.append(info.f)
     mu_seq = R / sum(service)
     log(f"serving: sequential {mu_seq:.1f} solves/s")
-    out = {"requests": R, "slots": args.serve_slots,
+    out = {"requests": R, "slots": args.serve_slots, "ticks_per_poll": args.serve_ticks,
+           "graph": bool(args.serve_graph),
            "sequential_fp32": {"solves_per_s": mu_seq}, "loads": []}
     for li, load in enumerate(float(x) for x in str(args.serve_load).split(",")):
         lam = load * mu_seq
@@ -146,7 +147,7 @@ def serve_bench(args) -> dict:
         lat_seq = np.asarray(fin) - arrivals
         done = {}
         with fc.Server(max_active=args.serve_slots, hbm_budget=args.serve_budget_gb * 2**30,
-                       ticks_per_poll=4) as sv:
+                       ticks_per_poll=args.serve_ticks, use_graph=bool(args.serve_graph)) as sv:
             t_start = fc.Server.clock()
             k = 0
             while len(done) < R:
@@ -202,7 +203,8 @@ def mixed_target_bench(args) -> dict:
     log(f"mixed target: nnz={wl.nnz:,}")
     # tau = 1/L_thm with ||S||_F for ||S||_2, as the paper's experiments do
     with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 32, wl.U0, precision="fp32", step=0.0,
-                   norm_estimate="frobenius", reorder=args.reorder) as s:
+                   norm_estimate="frobenius", reorder=args.reorder,
+                   defer_loss=bool(args.defer_loss)) as s:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = s.step(K)
@@ -218,7 +220,7 @@ def mixed_target_bench(args) -> dict:
     log(f"mixed target: FP32 {K} iterations in {t_fp32:.2f} s, f={f_k_check:.9e}, target {target:.9e}")
     elapsed, it, f_mixed = 0.0, 0, math.inf
     with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 32, wl.U0, precision="mixed", step=tau,
-                   reorder=args.reorder) as s:
+                   reorder=args.reorder, defer_loss=bool(args.defer_loss)) as s:
         chunk = max(1, K - 5)
         while it < 2 * K:
             torch.cuda.synchronize()
@@ -250,6 +252,43 @@ def mixed_target_bench(args) -> dict:
     }
 
 
+def artificial_bench(args) -> dict:
+    """The paper's artificial two-cluster graph (section 5): 500,000 + 250,000
+    nodes of expected degree 1,200 and 1,600, 200 bridges, C = 2, S = A + I,
+    step 5e-7, every node starting in the second cluster; 10 iterations of GPA
+    and of FISTA, timed, and the share of nodes whose dominant membership is
+    their ground-truth cluster."""
+    import numpy as np
+    import torch
+    import paper_2506_04045_amd as fc
+    import workloads as W
+    log("artificial graph: generating")
+    wl = W.two_cluster_er(args.seed, device="cuda")
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    labels = wl.meta["labels"].numpy()
+    out = {"workload": (f"two-cluster ER (500,000 + 250,000 nodes, expected degrees 1,200 / "
+                        f"1,600, 200 bridges), {wl.nnz:,} stored nnz, C=2, S=A+I, tau=5e-7, "
+                        f"start: every node in cluster 2, articles relabelled: {args.reorder}")}
+    for name, acc in (("gpa", False), ("fista", True)):
+        with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 2, wl.U0, accelerate=acc, step=5e-7,
+                       reorder=args.reorder, defer_loss=bool(args.defer_loss)) as s:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.step(10)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            U = s.get_u().cpu().numpy()
+        hit = float(np.mean(np.argmax(U, axis=1) == labels))
+        out[name] = {"iters": 10, "seconds": dt, "iters_per_s": 10 / dt, "f": info.f,
+                     "dominant_matches_ground_truth": max(hit, 1.0 - hit)}
+        log(f"artificial graph: {name} 10 iterations in {dt:.3f} s, "
+            f"{out[name]['dominant_matches_ground_truth']:.6f} of nodes recovered")
+    del wl
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__,
                                  formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -261,6 +300,10 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp32", "mixed"], default="fp32")
     ap.add_argument("--reorder", choices=["none", "degree"], default="degree",
                     help="internal renumbering of the articles (set up in fc_create, untimed)")
+    ap.add_argument("--defer-loss", type=int, default=1,
+                    help="1: each iterate's loss is formed during the next pass (fc_options.defer_loss)")
+    ap.add_argument("--no-artificial", action="store_true",
+                    help="skip the artificial two-cluster graph run")
     ap.add_argument("--target-iters", type=int, default=100,
                     help="K of the mixed-precision time-to-target measurement (0 disables it)")
     ap.add_argument("--seed", type=int, default=0)
@@ -275,6 +318,10 @@ def main() -> int:
                     help="arrival rates as multiples of the sequential solve rate (comma list)")
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-ticks", type=int, default=16,
+                    help="batched iterations the serving worker launches between state polls")
+    ap.add_argument("--serve-graph", type=int, default=0,
+                    help="1: replay each tick as a captured hipGraph")
     ap.add_argument("--serve-timeout", type=float, default=600.0)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain elementwise copy of this many MiB (read + write), "
@@ -326,7 +373,8 @@ def main() -> int:
     prec = args.precision
     t0 = time.perf_counter()
     solver = fc.Solver(wl.row_ptr, wl.col_idx, wl.val, args.c, wl.U0, precision=prec,
-                       accelerate=True, step=0.0, reorder=args.reorder)
+                       accelerate=True, step=0.0, reorder=args.reorder,
+                       defer_loss=bool(args.defer_loss))
     torch.cuda.synchronize()
     log(f"solver created in {time.perf_counter() - t0:.1f} s")
 
@@ -355,7 +403,7 @@ def main() -> int:
     kernels["reduce"] = {"avg_ms": avg["reduce"]}
     kernels["control"] = {"avg_ms": avg["control"]}
     dom = max(("spmm", "fused"), key=lambda k: avg[k])
-    wkey = f"powerlaw_n{n}_c{c}_{prec}_{args.reorder}"
+    wkey = f"powerlaw_n{n}_c{c}_{prec}_{args.reorder}" + ("_deferred" if args.defer_loss else "")
     traffic = measured_traffic(dom, wkey)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["achieved_GBps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -369,6 +417,9 @@ def main() -> int:
     mixed_target = None
     if args.target_iters > 0:
         mixed_target = mixed_target_bench(args)
+    artificial = None
+    if not args.no_artificial:
+        artificial = artificial_bench(args)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, c, n, nnz)
@@ -392,8 +443,10 @@ def main() -> int:
             "workload": (f"power-law fuzzy clustering n={n:,} c={c}: Chung-Lu pattern "
                          f"(exponent 2.1, mean degree 20, max 50,000), {nnz:,} stored nnz, "
                          f"planted communities sigma 0.05, unit diagonal, FISTA constant step "
-                         f"1/L (Theorem 3.1), {prec}, articles relabelled: {args.reorder}"),
-            "n": n, "c": c, "nnz": nnz, "precision": prec, "reorder": args.reorder, "tau": tau,
+                         f"1/L (Theorem 3.1), {prec}, articles relabelled: {args.reorder}, "
+                         f"loss evaluation deferred: {bool(args.defer_loss)}"),
+            "n": n, "c": c, "nnz": nnz, "precision": prec, "reorder": args.reorder,
+            "defer_loss": bool(args.defer_loss), "tau": tau,
             "f0": f0, "f_end": f_end,
         },
         "kernels": kernels,
@@ -401,6 +454,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "serving": serving,
         "mixed_time_to_target": mixed_target,
+        "artificial_two_cluster": artificial,
     }
     print(json.dumps(out), flush=True)
     return 0

@@ -122,6 +122,8 @@ typedef struct {
     int32_t step_schedule_len;
     int32_t reorder;           /* fc_reorder: FC_REORDER_NONE (default) or
                                   FC_REORDER_DEGREE, see below */
+    int32_t defer_loss;        /* 1: deferred loss evaluation, see below (default 0) */
+    int32_t reserved2;
 } fc_options;
 
 /* Internal numbering of the articles.  FC_REORDER_DEGREE renumbers them by
@@ -137,6 +139,23 @@ typedef struct {
  * in the sparse product.  Checkpoints record the choice: fc_set_state
  * rejects a state taken with the other numbering. */
 typedef enum { FC_REORDER_NONE = 0, FC_REORDER_DEGREE = 1 } fc_reorder;
+
+/* Deferred loss evaluation (defer_loss = 1, constant or scheduled steps only:
+ * backtracking needs each trial's loss at once and rejects it).  The
+ * structured loss of Alg. 3 needs sum_i <x_i, (S X)_i> for every accepted
+ * iterate.  By default the sparse product forms these terms as it writes
+ * S Xbar_n, which makes it read Xbar_n's own rows once more.  With
+ * defer_loss = 1 the product stores only the off-diagonal part S_off Xbar_n
+ * and the next fused pass, which reads Xbar_n and that product anyway, adds
+ * the unit diagonal back (S_eff Y = S_off Y + Y) and forms the terms; the
+ * loss of the last iterate of an fc_step or fc_solve call is formed by one
+ * extra pass over Xbar and its product before the call returns.  Every
+ * loss is still computed and logged; the loss stop test runs when the loss
+ * is known, so a stop at iteration k discards the trial computed from
+ * Xbar_k and returns Xbar_k with the same iteration count, loss and stop
+ * reason as the default mode.  Iterates agree with the default mode to
+ * rounding.  Checkpoints record the mode; the serving engine does not
+ * accept it (FC_ERR_UNSUPPORTED). */
 
 /* Per-solver progress, returned by fc_step and fc_solve. */
 typedef struct {

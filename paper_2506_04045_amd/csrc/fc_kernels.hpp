@@ -105,12 +105,18 @@ struct DevState {
     double tau0;            // constant step
     double tr_y_last;       // diagnostics of the last trial
     double df_last, rhs_last;
+    // deferred loss evaluation (fixed steps): the loss of an accepted iterate
+    // is formed during the next trial, from the terms <x_i, (S X)_i> that the
+    // fused kernel accumulates while it reads the iterate and its product
+    int32_t defer;          // 1: deferred evaluation
+    int32_t f_known;        // 1: f holds f(Xbar_iter)
+    double gsq_c;           // ||Xbar_iter^T Xbar_iter||_F^2, saved at acceptance
 };
 
 // Partial-sum layout of the fused kernel: three CPM x CPM matrices
 // (Gram of the trial point, Gram of the next extrapolated point, and the
 // line-search cross sum (p + y)^T (p - y)) followed by FUSED_NSCAL scalars.
-enum { FS_TRY = 0, FS_LIN = 1, FS_SQ = 2, FS_CORR = 3, FS_BAD = 4, FUSED_NSCAL = 8 };
+enum { FS_TRY = 0, FS_LIN = 1, FS_SQ = 2, FS_CORR = 3, FS_BAD = 4, FS_TRC = 5, FUSED_NSCAL = 8 };
 template <int CPM> struct FusedLayout {
     static constexpr int MAT = CPM * CPM;
     static constexpr int NE = 3 * MAT + FUSED_NSCAL;
@@ -151,6 +157,8 @@ struct Inst {
     double *part_spmm;
     double *red_mats;
     int32_t g_fused, g_spmm, g_comb, g_red;
+    int32_t defer;   // 1: products hold S_off X (no unit diagonal, no trace terms)
+    int32_t pad0;
     const double *sched;
     double *hist_f, *hist_tau, *hist_r;
     int32_t *hist_trials;
@@ -175,19 +183,27 @@ __device__ __forceinline__ bool inst_active(const Inst &I) { return !I.st || I.s
 __device__ __forceinline__ void reduce_cols_body(const double *__restrict__ in, int64_t np,
                                                  int64_t ld, int64_t ne, double *__restrict__ out,
                                                  int eb, int64_t blk) {
+    // eb entries per workgroup, 256 / eb fixed chunks of the np partial rows;
+    // every thread keeps four interleaved sums so its loads overlap.  The
+    // order of all additions is fixed, so the result is reproducible.
     __shared__ double sh[256];
     const int tid = threadIdx.x;
     const int el = tid % eb, chunk = tid / eb, nchunk = 256 / eb;
     const int64_t e = blk * eb + el;
-    double acc = 0.0;
+    double a4[4] = {0.0, 0.0, 0.0, 0.0};
     if (e < ne) {
         const int64_t per = (np + nchunk - 1) / nchunk;
         const int64_t p0 = chunk * per;
         const int64_t p1 = p0 + per < np ? p0 + per : np;
-        for (int64_t p = p0; p < p1; ++p)
-            acc += in[p * ld + e];
+        int64_t p = p0;
+        for (; p + 4 <= p1; p += 4)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                a4[j] += in[(p + j) * ld + e];
+        for (int j = 0; p < p1; ++p, ++j)
+            a4[j] += in[p * ld + e];
     }
-    sh[tid] = acc;
+    sh[tid] = (a4[0] + a4[1]) + (a4[2] + a4[3]);
     __syncthreads();
     if (chunk == 0 && e < ne) {
         double s = sh[el];
@@ -205,11 +221,12 @@ __global__ __launch_bounds__(256) void k_reduce_cols(const double *__restrict__ 
 }
 
 // The fused kernel's partial sums of one instance: entries split in blocks of
-// 64, each reduced over the instance's g_fused workgroup partials.
+// FUSED_RED_EB, each reduced over the instance's g_fused workgroup partials.
+constexpr int FUSED_RED_EB = 16;
 template <int CPM>
 __device__ __forceinline__ void reduce_fused_body(const Inst &I, int64_t blk) {
     constexpr int NE = FusedLayout<CPM>::NE;
-    reduce_cols_body(I.part_fused, I.g_fused, NE, NE, I.red_mats, 64, blk);
+    reduce_cols_body(I.part_fused, I.g_fused, NE, NE, I.red_mats, FUSED_RED_EB, blk);
 }
 template <int CPM> __global__ __launch_bounds__(256) void k_reduce_fused_1(Inst I) {
     if (inst_active(I))
@@ -581,9 +598,13 @@ __device__ __forceinline__ void team_slot_sum(TA (&acc)[NE]) {
 template <int GS, typename TA, typename TZ, typename TX, int CP, int NE>
 __device__ __forceinline__ double row_epilogue(bool live, int slot, int sub, int64_t row,
                                                const TX *__restrict__ X, TZ *__restrict__ Z,
-                                               int diag_unit, TA (&acc)[NE]) {
+                                               int diag_unit, int plain, TA (&acc)[NE]) {
     double d = 0.0;
-    if (live && slot == 0) {
+    if (live && slot == 0 && plain) {   // off-diagonal product only
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            __builtin_nontemporal_store((TZ)acc[q], &Z[row * CP + sub * NE + q]);
+    } else if (live && slot == 0) {
         TA xi[NE];
 #pragma unroll
         for (int q = 0; q < NE; ++q)
@@ -604,7 +625,8 @@ __device__ __forceinline__ double row_epilogue(bool live, int slot, int sub, int
     return (live && slot == 0 && sub == 0) ? d : 0.0;
 }
 
-// Z = S_eff U for one instance.
+// Z = S_eff U for one instance (S_off U, the stored entries only, with no
+// terms <u_i, z_i>, when the loss evaluation is deferred).
 //   light rows  (<= SPMM_LIGHT_MAX nonzeros): two-slot teams, in a
 //               grid-stride loop over blocks of ROWS_PER_WG rows;
 //   medium rows (listed in med_rows): one eight-slot team each;
@@ -631,7 +653,7 @@ __device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, 
     const int32_t *__restrict__ col = I.col;
     const VS *__restrict__ val = (const VS *)I.val;
     const int64_t n = I.n, light_max = I.light_max;
-    const int diag_unit = I.diag_unit;
+    const int diag_unit = I.diag_unit, plain = I.defer;
     const int tid = threadIdx.x;
     double trace_acc = 0.0;
 
@@ -654,7 +676,8 @@ __device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, 
                     team_row_sum<TU, VS, CP, Lc::SLOTS, DEPTH>(col, val, U, beg, end, slot, sub, acc);
             }
             team_slot_sum<Lc::GS, Lc::TEAM>(acc);
-            trace_acc += row_epilogue<Lc::GS, TA, TZ, TX, CP>(live, slot, sub, row, X, Z, diag_unit, acc);
+            trace_acc += row_epilogue<Lc::GS, TA, TZ, TX, CP>(live, slot, sub, row, X, Z, diag_unit,
+                                                              plain, acc);
         }
     }
     {   // medium rows, then the chunks of heavy rows
@@ -670,7 +693,8 @@ __device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, 
             team_row_sum<TU, VS, CP, Wc::SLOTS, DEPTH>(col, val, U, row_ptr[row], row_ptr[row + 1],
                                                         slot, sub, acc);
             team_slot_sum<Wc::GS, Wc::TEAM>(acc);
-            trace_acc += row_epilogue<Wc::GS, TA, TZ, TX, CP>(true, slot, sub, row, X, Z, diag_unit, acc);
+            trace_acc += row_epilogue<Wc::GS, TA, TZ, TX, CP>(true, slot, sub, row, X, Z, diag_unit,
+                                                              plain, acc);
         }
         const int64_t *__restrict__ chunk_beg = I.chunk_beg;
         const int32_t *__restrict__ chunk_len = I.chunk_len;
@@ -745,11 +769,15 @@ __device__ __forceinline__ void combine_body(const Inst &I, int role, int64_t bl
             TA acc = (TA)0;
             for (int32_t q = heavy_chunk_ptr[h]; q < heavy_chunk_ptr[h + 1]; ++q)
                 acc += chunk_sum[(int64_t)q * CP + k];
-            const TA xi = (TA)X[row * CP + k];
-            if (diag_unit)
-                acc += xi;
-            Z[row * CP + k] = (TZ)acc;
-            trace_acc += (double)acc * (double)xi;
+            if (I.defer) {
+                Z[row * CP + k] = (TZ)acc;
+            } else {
+                const TA xi = (TA)X[row * CP + k];
+                if (diag_unit)
+                    acc += xi;
+                Z[row * CP + k] = (TZ)acc;
+                trace_acc += (double)acc * (double)xi;
+            }
         }
     }
     sh[tid] = trace_acc;
@@ -920,6 +948,47 @@ __device__ __forceinline__ double simplex_threshold(const T (&v)[NC], const bool
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t nwt_of(int64_t n) { return (n + 63) / 64; }
 
+// A lane's terms x_k (S_eff x)_k of the loss, from a row of the iterate and of
+// its off-diagonal product (padded and missing components are zero): summed
+// in the compute type over the lane's components (explicit FMAs, so every
+// kernel that calls this forms the same value), then carried in double.
+template <typename T, int NC>
+__device__ __forceinline__ double trace_terms(const T (&x)[NC], const T (&z)[NC], int diag_unit) {
+    T a = (T)0;
+#pragma unroll
+    for (int s = 0; s < NC; ++s) {
+        const T zd = diag_unit ? z[s] + x[s] : z[s];
+        a = fma(x[s], zd, a);
+    }
+    return (double)a;
+}
+
+// The fused kernel's scalars of one workgroup: a tree over each wave, then the
+// four waves added in order; scalar k goes to out[k], unused slots get zero.
+template <int N>
+__device__ __forceinline__ void fused_scalars_out(double (&vals)[N], double *__restrict__ out) {
+    __shared__ double shs[4][FUSED_NSCAL];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            vals[k] += shfl_xor_d(vals[k], off);
+    }
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < N; ++k)
+            shs[wave][k] = vals[k];
+    __syncthreads();
+    if (tid < FUSED_NSCAL) {
+        double sum = 0.0;
+        if (tid < N)
+            sum = ((shs[0][tid] + shs[1][tid]) + shs[2][tid]) + shs[3][tid];
+        out[tid] = sum;
+    }
+    __syncthreads();
+}
+
 template <typename T, int CP, bool ACCEL, bool BT, bool SHADOW>
 __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t nblk) {
     constexpr int CPM = CP < 16 ? 16 : CP;
@@ -957,17 +1026,31 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
     const T bn1 = (T)(1.0 + beta_next), bn0 = (T)beta_next;
     const bool use_prev = ACCEL && beta != 0.0;
 
-    // A operands of Y G: G[16a + r][k(s)] for every block a and slot s
-    T gA[M][NC];
+    // A operands of Y G: G[16a + r][k(s)] for every block a and slot s.  FP32
+    // keeps G_Y in LDS (row stride CPM + 1 spreads the 16 rows a read touches
+    // over the banks) and reads the operands next to their use, which keeps
+    // the kernel within 128 registers; FP64 holds them in registers.
+    constexpr bool G_LDS = sizeof(T) == 4;
+    constexpr int GSTR = CPM + 1;
+    __shared__ T gsh[G_LDS ? CPM * GSTR : 1];
+    T gA[G_LDS ? 1 : M][G_LDS ? 1 : NC];
+    if constexpr (G_LDS) {
+        for (int e = tid; e < CPM * CPM; e += 256)
+            gsh[(e / CPM) * GSTR + e % CPM] = GYs[e];
+        __syncthreads();
+    } else {
 #pragma unroll
-    for (int a = 0; a < M; ++a)
+        for (int a = 0; a < M; ++a)
 #pragma unroll
-        for (int s = 0; s < NC; ++s)
-            gA[a][s] = GYs[(16 * a + r) * CPM + kslot<T>(s, g)];
+            for (int s = 0; s < NC; ++s)
+                gA[a][s] = GYs[(16 * a + r) * CPM + kslot<T>(s, g)];
+    }
 
     __shared__ T lds[NMAT][64 * STRIDE];
 
-    double sc_try = 0.0, sc_lin = 0.0, sc_sq = 0.0, sc_corr = 0.0, sc_bad = 0.0;
+    double sc_try = 0.0, sc_lin = 0.0, sc_sq = 0.0, sc_corr = 0.0, sc_trc = 0.0;
+    int32_t n_bad = 0;   // non-finite step values
+    const int defer = I.defer, diag_unit = I.diag_unit;
     doublex4 acc64[BPW];
 #pragma unroll
     for (int k = 0; k < BPW; ++k)
@@ -1031,20 +1114,32 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
         const bool live = row < n;
         T xc[NC], xp[NC], zc[NC], zp[NC];
         load_tile(wt, xc, zc, xp, zp);
+        if (defer)   // the current iterate's terms <x_i, (S_eff X)_i> for its loss
+            sc_trc += trace_terms<T, NC>(xc, zc, diag_unit);
         T y[NC], sy[NC];
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
             y[s] = use_prev ? b1 * xc[s] - b0 * xp[s] : xc[s];
             sy[s] = use_prev ? b1 * zc[s] - b0 * zp[s] : zc[s];
         }
+        if (defer && diag_unit)   // the stored products lack the unit diagonal
+#pragma unroll
+            for (int s = 0; s < NC; ++s)
+                sy[s] += y[s];
         // Y (G_Y - mu 1 1^T) on the matrix cores, returned in the lane layout of y
         T yg[NC];
 #pragma unroll
         for (int a = 0; a < M; ++a) {
             A4 acc = A4{0, 0, 0, 0};
 #pragma unroll
-            for (int s = 0; s < NC; ++s)
-                acc = mfma16x16x4(gA[a][s], y[s], acc);
+            for (int s = 0; s < NC; ++s) {
+                T ga;
+                if constexpr (G_LDS)
+                    ga = gsh[(16 * a + r) * GSTR + kslot<T>(s, g)];
+                else
+                    ga = gA[a][s];
+                acc = mfma16x16x4(ga, y[s], acc);
+            }
 #pragma unroll
             for (int q = 0; q < 4; ++q)
                 yg[4 * a + q] = acc[q];
@@ -1075,7 +1170,7 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
                     ysum += (double)y[s];
                 }
                 if (!(v[s] == v[s]) || v[s] - v[s] != (T)0)
-                    sc_bad += 1.0;
+                    n_bad += 1;
             }
         }
         if (BT) {
@@ -1175,31 +1270,19 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
             }
         }
     }
-    // scalars: wave tree, then the four waves in order
-    __shared__ double shs[4][FUSED_NSCAL];
-    double vals[5] = {sc_try, sc_lin, sc_sq, sc_corr, sc_bad};
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            vals[k] += shfl_xor_d(vals[k], off);
-    }
-    if (lane == 0)
-#pragma unroll
-        for (int k = 0; k < 5; ++k)
-            shs[wave][k] = vals[k];
-    __syncthreads();
-    if (tid < FUSED_NSCAL) {
-        double s = 0.0;
-        if (tid < 5)
-            s = ((shs[0][tid] + shs[1][tid]) + shs[2][tid]) + shs[3][tid];
-        out[3 * L::MAT + tid] = s;
-    }
-    __syncthreads();
+    double vals[6] = {sc_try, sc_lin, sc_sq, sc_corr, (double)n_bad, sc_trc};
+    fused_scalars_out(vals, out + 3 * L::MAT);
+}
+
+// FP32 up to 32 clusters without the line-search sums fits 128 registers:
+// ask for four waves per SIMD (measured 6 % faster at c = 32 than the three
+// the compiler picks alone).
+template <typename T, int CP, bool BT> constexpr int fused_min_waves() {
+    return sizeof(T) == 4 && !BT && CP <= 32 ? 4 : 1;
 }
 
 template <typename T, int CP, bool ACCEL, bool BT, bool SHADOW>
-__global__ __launch_bounds__(256) void k_fused_1(Inst I) {
+__global__ __launch_bounds__(256, (fused_min_waves<T, CP, BT>())) void k_fused_1(Inst I) {
     if (inst_active(I))
         fused_body<T, CP, ACCEL, BT, SHADOW>(I, blockIdx.x, gridDim.x);
 }
@@ -1214,6 +1297,44 @@ __global__ __launch_bounds__(256) void k_fused_b(const Inst *__restrict__ insts,
         if (inst_active(I))
             fused_body<T, CP, ACCEL, BT, SHADOW>(I, t.blk, I.g_fused);
     }
+}
+
+// Deferred loss of the current iterate: the terms <x_i, (S_eff X)_i> as the
+// fused kernel forms them (same tiles, lanes, order and grid), written to
+// the same scalar slot of the same partial rows.
+template <typename T, int CP>
+__global__ __launch_bounds__(256) void k_trace_fused(Inst I) {
+    constexpr int CPM = CP < 16 ? 16 : CP;
+    constexpr int M = CPM / 16;
+    constexpr int NC = 4 * M;
+    using L = FusedLayout<CPM>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const T *__restrict__ Xc = (const T *)I.X[I.st->role[ROLE_C]];
+    const T *__restrict__ Zc = (const T *)I.Z[I.st->role[ROLE_C]];
+    const int64_t n = I.n, nwt = nwt_of(n);
+    double sc_trc = 0.0;
+    for (int64_t wt = blockIdx.x; wt < nwt; wt += gridDim.x) {
+        const int64_t row = wt * 64 + wave * 16 + r;
+        T xc[NC], zc[NC];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int k = kslot<T>(s, g);
+            const bool ok = row < n && k < CP;
+            xc[s] = ok ? Xc[row * CP + k] : (T)0;
+            zc[s] = ok ? Zc[row * CP + k] : (T)0;
+        }
+        sc_trc += trace_terms<T, NC>(xc, zc, I.diag_unit);
+    }
+    double vals[6] = {0.0, 0.0, 0.0, 0.0, 0.0, sc_trc};
+    fused_scalars_out(vals, I.part_fused + (int64_t)blockIdx.x * L::NE + 3 * L::MAT);
+}
+
+// One entry of the fused partials reduced exactly as reduce_fused_body does
+// (same chunks of partial rows, same order).
+template <int CPM> __global__ __launch_bounds__(256) void k_reduce_fused_entry(Inst I, int entry) {
+    using L = FusedLayout<CPM>;
+    reduce_cols_body(I.part_fused + entry, I.g_fused, L::NE, 1, I.red_mats + entry, FUSED_RED_EB, 0);
 }
 
 // ---------------------------------------------------------------------------
@@ -1237,6 +1358,8 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
     int32_t *__restrict__ hist_trials = I.hist_trials;
     double *__restrict__ hist_r = I.hist_r;
     const int tid = threadIdx.x;
+    // mode 0: initial evaluation; 1: after a trial; 2: deferred evaluation of
+    // the current iterate after the trials (nothing else changes)
     if (mode == 1 && !st->active)
         return;
     // the products' terms sum_i <x_i, (S X)_i>: workgroup partials of the
@@ -1289,7 +1412,9 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
     __syncthreads();
 
     if (tid == 0) {
-        const double tr_p = tr_total;
+        // deferred: the products carry no terms; the fused kernel (or the
+        // evaluation pass) summed them for the current iterate
+        const double tr_p = st->defer ? sc[FS_TRC] : tr_total;
         const double f_p = st->s2 + gp_sq - 2.0 * tr_p;
         int accept = 1;
         if (mode == 0) {
@@ -1298,6 +1423,8 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
             st->iter = 0;
             st->trials = 0;
             st->trial_in_iter = 1;
+            st->f_known = 1;
+            st->gsq_c = gp_sq;
             if (hist_f)
                 hist_f[0] = f_p;
             if (!(f_p == f_p) || f_p - f_p != 0.0) {
@@ -1306,11 +1433,37 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
                 st->active = 0;
                 accept = 0;
             }
-        } else {
+        } else if (mode == 2 || (st->defer && !st->f_known)) {
+            // deferred loss of Xbar_iter: ||G||^2 saved when it was accepted
+            accept = mode == 1;
+            if (!st->f_known) {
+                const double f_c = st->s2 + st->gsq_c - 2.0 * sc[FS_TRC];
+                st->f = f_c;
+                st->f_known = 1;
+                if (st->iter < st->hist_cap && hist_f)
+                    hist_f[st->iter] = f_c;
+                if (!(f_c == f_c) || f_c - f_c != 0.0) {
+                    st->error = ERR_NONFINITE;
+                    st->stop_reason = STOP_ERROR;
+                    st->active = 0;
+                    accept = 0;
+                } else if (st->iter >= 1 && st->tol_loss == st->tol_loss &&
+                           st->f_prev - f_c <= st->tol_loss) {
+                    // the loss test of Alg. 3/4 for Xbar_iter: stop there and
+                    // drop the trial computed from it
+                    st->stop_reason = STOP_LOSS;
+                    st->active = 0;
+                    accept = 0;
+                }
+            }
+        }
+        if (mode == 1 && accept) {
             const double tr_y = sc[FS_TRY], lin_s = sc[FS_LIN], sq = sc[FS_SQ];
             const double corr = sc[FS_CORR], bad = sc[FS_BAD];
             st->trials += 1;
-            const bool finite = (f_p == f_p) && (f_p - f_p == 0.0) && bad == 0.0;
+            // deferred: f_p is not this trial's loss; check what it provides
+            const double f_chk = st->defer ? gp_sq : f_p;
+            const bool finite = (f_chk == f_chk) && (f_chk - f_chk == 0.0) && bad == 0.0;
             if (!finite) {
                 st->error = ERR_NONFINITE;
                 st->stop_reason = STOP_ERROR;
@@ -1330,12 +1483,17 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
                 const double rr = sqrt(sq) / st->tau;
                 st->iter = it;
                 st->f_prev = st->f;
-                st->f = f_p;
+                if (st->defer) {   // f(Xbar_it) follows from the next pass
+                    st->f_known = 0;
+                    st->gsq_c = gp_sq;
+                } else {
+                    st->f = f_p;
+                }
                 st->r = rr;
                 if (it == 1)
                     st->r1 = rr;
                 if (it < st->hist_cap) {
-                    if (hist_f) hist_f[it] = f_p;
+                    if (hist_f && !st->defer) hist_f[it] = f_p;
                     if (hist_tau) hist_tau[it] = st->tau;
                     if (hist_trials) hist_trials[it] = st->trial_in_iter;
                     if (hist_r) hist_r[it] = rr;
@@ -1356,8 +1514,8 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
                     st->beta_next = 0.0;
                 }
                 st->trial_in_iter = 1;
-                // stop tests
-                if (st->tol_loss == st->tol_loss && st->f_prev - st->f <= st->tol_loss) {
+                // stop tests (deferred: the loss test runs when f is formed)
+                if (!st->defer && st->tol_loss == st->tol_loss && st->f_prev - st->f <= st->tol_loss) {
                     st->stop_reason = STOP_LOSS;
                     st->active = 0;
                 } else if (st->tol_pgrad > 0.0 && rr <= st->tol_pgrad * st->r1) {

@@ -385,6 +385,7 @@ struct fc_solver {
     int max_iter = 100;
     double spec_norm = 0.0, L_thm = 0.0;
     int reorder = FC_REORDER_NONE;
+    int defer = 0;              // deferred loss evaluation (fixed steps)
     int32_t *d_perm = nullptr;  // internal row i is user row d_perm[i]
     int32_t *d_inv = nullptr;   // user row j is internal row d_inv[j]
     std::vector<void *> allocs;
@@ -462,6 +463,25 @@ fc_status launch_trial_t(fc_solver *h, hipEvent_t *ev) {
     return FC_OK;
 }
 
+// Deferred loss terms of the current iterate: the fused kernel's sums, formed
+// by the evaluation pass and reduced into the same entry.
+template <typename T, int CP>
+void launch_trace_t(fc_solver *h) {
+    constexpr int CPM = CP < 16 ? 16 : CP;
+    hipLaunchKernelGGL((k_trace_fused<T, CP>), dim3(h->g_fused), dim3(256), 0, h->stream, h->inst);
+    hipLaunchKernelGGL((k_reduce_fused_entry<CPM>), dim3(1), dim3(256), 0, h->stream, h->inst,
+                       3 * FusedLayout<CPM>::MAT + (int)FS_TRC);
+}
+
+template <typename T, int CP>
+fc_status launch_eval_t(fc_solver *h) {
+    constexpr int CPM = CP < 16 ? 16 : CP;
+    launch_trace_t<T, CP>(h);
+    hipLaunchKernelGGL((k_control_1<T, CPM>), dim3(1), dim3(256), 0, h->stream, h->inst, 2);
+    HIPCHK(hipGetLastError());
+    return FC_OK;
+}
+
 // Initial evaluation: Gram and product of Xbar_0, then the controller.
 template <typename T, typename TU, typename VS, int CP>
 fc_status launch_init_t(fc_solver *h) {
@@ -477,6 +497,8 @@ fc_status launch_init_t(fc_solver *h) {
                            h->n * h->cp);
     launch_reduce(h->d_part_gram, (int64_t)h->g_gram * 4, ld, ld, h->d_red_mats, s);
     launch_spmm<TU, T, T, VS, CP>(h->inst, (int)ROLE_C, s);
+    if (h->defer)
+        launch_trace_t<T, CP>(h);
     hipLaunchKernelGGL((k_control_1<T, CPM>), dim3(1), dim3(256), 0, s, h->inst, 0);
     HIPCHK(hipGetLastError());
     return FC_OK;
@@ -492,6 +514,15 @@ fc_status launch_trial(fc_solver *h, hipEvent_t *ev = nullptr) {
         if constexpr (CP >= 8)
             return launch_trial_t<float, __hip_bfloat16, __half, CP>(h, ev);
         return fail(FC_ERR_UNSUPPORTED, "mixed precision needs c >= 5 (padded width >= 8)");
+    });
+}
+
+fc_status launch_eval(fc_solver *h) {
+    return with_cp(h->cp, [&](auto cpc) -> fc_status {
+        constexpr int CP = decltype(cpc)::value;
+        if (h->prec == FC_PREC_FP64)
+            return launch_eval_t<double, CP>(h);
+        return launch_eval_t<float, CP>(h);
     });
 }
 
@@ -614,6 +645,14 @@ fc_status run_until(fc_solver *h, int32_t target, int32_t max_iter, EventLog *lo
     }
     if (log)
         HIPCHK(log->collect());
+    if (h->defer && !h->h.f_known && h->h.error == ERR_NONE) {
+        // the loss of the last accepted iterate
+        st = launch_eval(h);
+        if (st == FC_OK)
+            st = read_state(h);
+        if (st != FC_OK)
+            return st;
+    }
     return status_of(h);
 }
 
@@ -752,6 +791,10 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
         return fail(FC_ERR_INVALID_ARG, "norm_estimate must be 0 or 1");
     if (opt->reorder != FC_REORDER_NONE && opt->reorder != FC_REORDER_DEGREE)
         return fail(FC_ERR_INVALID_ARG, "unknown reorder mode");
+    if (opt->defer_loss != 0 && opt->defer_loss != 1)
+        return fail(FC_ERR_INVALID_ARG, "defer_loss must be 0 or 1");
+    if (opt->defer_loss && opt->step_rule != FC_STEP_FIXED)
+        return fail(FC_ERR_INVALID_ARG, "defer_loss needs FC_STEP_FIXED (backtracking tests each trial's loss)");
     if (U0 && u0_dtype != FC_F64 && u0_dtype != FC_F32)
         return fail(FC_ERR_INVALID_ARG, "U0 must be FC_F64 or FC_F32");
     if (opt->precision == FC_PREC_FP64 && S->values_dtype != FC_F64)
@@ -787,6 +830,7 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
     h->pooled = pooled;
     h->hist_cap = hist_cap;
     h->check_every = opt->check_every > 0 ? opt->check_every : 16;
+    h->defer = opt->defer_loss ? 1 : 0;
     h->max_iter = opt->max_iter;
     hipStream_t s = h->stream;
 
@@ -852,7 +896,15 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
 
     // launch geometry: persistent grids sized to the device
     const int cus = device_cus();
-    h->g_fused = grid_1d(h->n, 64, (int64_t)cus * 2);
+    // one row tile per workgroup up to 2 workgroups per CU; large single
+    // solves up to 12 per CU (three rounds at four resident) while keeping at
+    // least 8 tiles per workgroup; served instances stay at 2 per CU
+    {
+        int64_t cap = (int64_t)cus * 2;
+        if (!pooled)
+            cap = std::min<int64_t>((int64_t)cus * 12, std::max<int64_t>(cap, h->n / 512));
+        h->g_fused = grid_1d(h->n, 64, cap);
+    }
     h->g_gram = grid_1d(cdiv(h->n, 16), 4, (int64_t)cus * 2);
     {
         int rows_per_wg = 1;
@@ -872,7 +924,7 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
     if (st != FC_OK)
         return cleanup(st);
     h->g_comb = combine_grid(h->heavy.nheavy, 256 / h->cp);
-    h->g_red = (int)cdiv(fused_ne(h->cpm), 64);
+    h->g_red = (int)cdiv(fused_ne(h->cpm), FUSED_RED_EB);
     const int ne = fused_ne(h->cpm);
     if (h->alloc(&h->d_part_fused, sizeof(double) * (size_t)h->g_fused * ne) != hipSuccess ||
         h->alloc(&h->d_part_spmm, sizeof(double) * (size_t)(h->g_spmm + h->g_comb)) != hipSuccess ||
@@ -912,6 +964,7 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
         I.hist_r = h->d_hist_r;
         I.hist_trials = h->d_hist_trials;
         I.sched = nullptr;
+        I.defer = h->defer;
     }
     if (hipMemsetAsync(h->d_red_mats, 0, sizeof(double) * ne, s) != hipSuccess ||
         hipMemsetAsync(h->d_hist_trials, 0, sizeof(int32_t) * h->hist_cap, s) != hipSuccess)
@@ -993,6 +1046,8 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
     d.max_iter = INT_MAX;
     d.accelerate = h->accelerate;
     d.backtrack = h->backtrack;
+    d.defer = h->defer;
+    d.f_known = 1;
     d.c = h->c;
     d.hist_cap = h->hist_cap;
     d.sched_len = h->sched_len;
@@ -1157,6 +1212,7 @@ struct CkptHeader {
     int64_t n;
     int32_t c, cp, prec, accelerate, backtrack, diag;
     int32_t hist_len, reorder;
+    int32_t defer, reserved;
     DevState st;
 };
 constexpr uint64_t CKPT_MAGIC = 0x3130545043434646ull;  // "FFCCPT01"
@@ -1189,7 +1245,7 @@ fc_status fc_get_state(const fc_solver *h, void *buf, size_t *bytes) {
     hipStream_t s = h->stream;
     CkptHeader hd = {};
     hd.magic = CKPT_MAGIC;
-    hd.version = 1;
+    hd.version = 2;
     hd.header_bytes = sizeof(CkptHeader);
     hd.n = h->n;
     hd.c = h->c;
@@ -1199,6 +1255,7 @@ fc_status fc_get_state(const fc_solver *h, void *buf, size_t *bytes) {
     hd.backtrack = h->backtrack;
     hd.diag = (int32_t)h->diag;
     hd.reorder = h->reorder;
+    hd.defer = h->defer;
     hd.hist_len = hist_len;
     hd.st = h->h;
     char *p = (char *)buf;
@@ -1234,11 +1291,11 @@ fc_status fc_set_state(fc_solver *h, const void *buf, size_t bytes) {
         return fail(FC_ERR_INVALID_ARG, "checkpoint buffer too small");
     CkptHeader hd;
     std::memcpy(&hd, buf, sizeof(hd));
-    if (hd.magic != CKPT_MAGIC || hd.version != 1 || hd.header_bytes != sizeof(CkptHeader))
+    if (hd.magic != CKPT_MAGIC || hd.version != 2 || hd.header_bytes != sizeof(CkptHeader))
         return fail(FC_ERR_INVALID_ARG, "not a checkpoint of this library version");
     if (hd.n != h->n || hd.c != h->c || hd.cp != h->cp || hd.prec != (int32_t)h->prec ||
         hd.accelerate != h->accelerate || hd.backtrack != h->backtrack || hd.diag != (int32_t)h->diag ||
-        hd.reorder != h->reorder)
+        hd.reorder != h->reorder || hd.defer != h->defer)
         return fail(FC_ERR_INVALID_ARG, "checkpoint was taken from a solver with other n, c or options");
     if (hd.hist_len < 1 || hd.hist_len > h->hist_cap || bytes < ckpt_bytes(h, hd.hist_len))
         return fail(FC_ERR_INVALID_ARG, "checkpoint buffer truncated");

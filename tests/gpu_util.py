@@ -49,3 +49,29 @@ def star_plus_er(n, avg_deg, seed, hub_frac=1.0):
         rp2.append(len(ci2))
     return (np.array(rp2, dtype=np.int64), np.array(ci2, dtype=np.int32),
             np.array(v2, dtype=np.float64))
+
+
+def sample_rows(row_ptr, seed, k=2000):
+    """Random articles plus the 8 largest rows and rows of each length class
+    (at most 64, 65-2,048, more than 2,048 nonzeros); sorted, distinct."""
+    deg = (row_ptr[1:] - row_ptr[:-1]).cpu().numpy()
+    rng = np.random.default_rng(seed)
+    rows = [rng.integers(0, deg.shape[0], k), np.argsort(deg)[-8:]]
+    for lo, hi in ((0, 0), (1, 64), (65, 2048), (2049, 1 << 40)):
+        cand = np.flatnonzero((deg >= lo) & (deg <= hi))
+        if cand.size:
+            rows.append(rng.choice(cand, min(64, cand.size), replace=False))
+    return np.unique(np.concatenate(rows)).astype(np.int64)
+
+
+def sub_csr(row_ptr, col_idx, val, rows):
+    """Rows `rows` of the device CSR, copied to the host."""
+    r = torch.from_numpy(rows).to(row_ptr.device)
+    beg, lens = row_ptr[r], row_ptr[r + 1] - row_ptr[r]
+    sub_rp = torch.zeros(rows.shape[0] + 1, dtype=torch.int64, device=row_ptr.device)
+    torch.cumsum(lens, 0, out=sub_rp[1:])
+    total = int(sub_rp[-1])
+    owner = torch.repeat_interleave(torch.arange(rows.shape[0], device=row_ptr.device), lens)
+    idx = beg[owner] + (torch.arange(total, device=row_ptr.device) - sub_rp[owner])
+    return (sub_rp.cpu().numpy(), col_idx[idx].cpu().numpy(),
+            val[idx].double().cpu().numpy())

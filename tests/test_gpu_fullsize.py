@@ -20,6 +20,7 @@ import torch
 
 import oracle
 import workloads as W
+from tests.gpu_util import sample_rows as _sample, sub_csr as _sub_csr
 
 pytestmark = [pytest.mark.gpu, pytest.mark.timeout(900)]
 
@@ -31,32 +32,6 @@ def fc():
     import paper_2506_04045_amd as fc
     fc.library_path()
     return fc
-
-
-def _sample(row_ptr, seed, k=2000):
-    """Random articles plus the 8 largest rows and rows of each length class
-    (at most 64, 65-2,048, more than 2,048 nonzeros); sorted, distinct."""
-    deg = (row_ptr[1:] - row_ptr[:-1]).cpu().numpy()
-    rng = np.random.default_rng(seed)
-    rows = [rng.integers(0, deg.shape[0], k), np.argsort(deg)[-8:]]
-    for lo, hi in ((0, 0), (1, 64), (65, 2048), (2049, 1 << 40)):
-        cand = np.flatnonzero((deg >= lo) & (deg <= hi))
-        if cand.size:
-            rows.append(rng.choice(cand, min(64, cand.size), replace=False))
-    return np.unique(np.concatenate(rows)).astype(np.int64)
-
-
-def _sub_csr(row_ptr, col_idx, val, rows):
-    """Rows `rows` of the device CSR, copied to the host."""
-    r = torch.from_numpy(rows).to(row_ptr.device)
-    beg, lens = row_ptr[r], row_ptr[r + 1] - row_ptr[r]
-    sub_rp = torch.zeros(rows.shape[0] + 1, dtype=torch.int64, device=row_ptr.device)
-    torch.cumsum(lens, 0, out=sub_rp[1:])
-    total = int(sub_rp[-1])
-    owner = torch.repeat_interleave(torch.arange(rows.shape[0], device=row_ptr.device), lens)
-    idx = beg[owner] + (torch.arange(total, device=row_ptr.device) - sub_rp[owner])
-    return (sub_rp.cpu().numpy(), col_idx[idx].cpu().numpy(),
-            val[idx].double().cpu().numpy())
 
 
 def _check_first_step(fc, wl, precision, val_for_oracle, seed, reorders=("degree",)):

@@ -53,11 +53,13 @@ def _solve_gpu(fc, rp, ci, v, U0, c, prec, iters, **kw):
     return info, U, hist
 
 
-def test_small_fp64_trajectory(fc, small):
+@pytest.mark.parametrize("defer", [False, True])
+def test_small_fp64_trajectory(fc, small, defer):
     d = small
     ref = oracle.solve(d["rp"], d["ci"], d["v"], True, d["U0"], accelerate=True, max_iter=200,
                        step=d["tau"])
-    info, U, hist = _solve_gpu(fc, d["rp"], d["ci"], d["v"], d["U0"], d["c"], "fp64", 200)
+    info, U, hist = _solve_gpu(fc, d["rp"], d["ci"], d["v"], d["U0"], d["c"], "fp64", 200,
+                               defer_loss=defer)
     assert info.iter == 200
     # the device computed tau = 1/L_thm by its own power iteration
     assert hist["tau"][1] == pytest.approx(d["tau"], rel=1e-10)
@@ -65,13 +67,15 @@ def test_small_fp64_trajectory(fc, small):
     assert np.abs(U - ref.X).max() <= 1e-9
 
 
-def test_small_fp32_against_fp64_oracle(fc, small):
+@pytest.mark.parametrize("defer", [False, True])
+def test_small_fp32_against_fp64_oracle(fc, small, defer):
     d = small
     U0 = d["U0"].astype(np.float32).astype(np.float64)
     v = d["v"].astype(np.float32).astype(np.float64)
     ref = oracle.solve(d["rp"], d["ci"], v, True, U0, accelerate=True, max_iter=200,
                        step=d["tau"])
-    info, U, hist = _solve_gpu(fc, d["rp"], d["ci"], v, U0, d["c"], "fp32", 200, step=d["tau"])
+    info, U, hist = _solve_gpu(fc, d["rp"], d["ci"], v, U0, d["c"], "fp32", 200, step=d["tau"],
+                               defer_loss=defer)
     f_rel = abs(info.f - ref.f[-1]) / abs(ref.f[-1])
     df_ref = ref.f[0] - ref.f[-1]
     df_rel = abs((hist["f"][0] - info.f) - df_ref) / abs(df_ref)
@@ -101,6 +105,7 @@ def test_uniform_start_is_a_fixed_point(fc, small):
 @pytest.mark.parametrize("accelerate", [False, True])
 @pytest.mark.parametrize("c", [1, 3, 17, 33, 64])
 def test_fp64_parity_shapes(fc, diag, accelerate, c):
+    defer = (c + accelerate + (diag == "unit")) % 2 == 1   # half the cases deferred
     n = 1000 + 41
     wl = W.er_planted(n, c, 8.0, 0.05, c, val_dtype=torch.float64, u_dtype=torch.float64)
     rp, ci, v, U0 = wl.numpy()
@@ -110,7 +115,7 @@ def test_fp64_parity_shapes(fc, diag, accelerate, c):
     tau = 2e-4
     ref = oracle.solve(rp, ci, v, diag == "unit", U0, accelerate=accelerate, max_iter=25, step=tau)
     info, U, hist = _solve_gpu(fc, rp, ci, v, U0, c, "fp64", 25, step=tau, diag=diag,
-                               accelerate=accelerate)
+                               accelerate=accelerate, defer_loss=defer)
     assert np.abs(hist["f"] - ref.f).max() <= 1e-9 * abs(ref.f[0])
     assert np.abs(U - ref.X).max() <= 1e-9
 
@@ -144,7 +149,8 @@ def test_fp32_replays_the_oracle_step_sequence(fc):
     assert agree >= 0.9
 
 
-def test_gpa_loss_stop_example41(fc):
+@pytest.mark.parametrize("defer", [False, True])
+def test_gpa_loss_stop_example41(fc, defer):
     ex = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "example41.json")))
     S = np.array(ex["S"], dtype=float)
     rp, ci, v = pins.csr_from_dense(S)
@@ -154,17 +160,20 @@ def test_gpa_loss_stop_example41(fc):
                        tol_loss=0.0)
     Sd = csr_to_dev(rp, ci, v, torch.float64)
     with fc.Solver(*Sd, 2, dev(X0, torch.float64), precision="fp64", diag="stored",
-                   accelerate=False, step=0.1, tol_loss=0.0, max_iter=5000) as s:
+                   accelerate=False, step=0.1, tol_loss=0.0, max_iter=5000,
+                   defer_loss=defer) as s:
         info = s.solve()
         U = s.get_u(torch.float64).cpu().numpy()
+        hist = s.history()
     assert info.stop_reason == 2  # FC_STOP_LOSS
-    assert info.iter == ref.iters
+    assert info.iter == ref.iters and info.trials == ref.iters
+    assert np.abs(hist["f"] - ref.f).max() <= 1e-12 * abs(ref.f[0])
     assert round(info.f, 2) == ex["scenario2"]["loss"]
     assert np.abs(U - ref.X).max() <= 1e-12
     # scenario 3: the uniform start stops after one iteration, unchanged
     X3 = np.full((7, 2), 0.5)
     with fc.Solver(*Sd, 2, dev(X3, torch.float64), precision="fp64", diag="stored",
-                   accelerate=False, step=0.1, tol_loss=0.0, max_iter=50) as s:
+                   accelerate=False, step=0.1, tol_loss=0.0, max_iter=50, defer_loss=defer) as s:
         info = s.solve()
         assert info.iter == 1 and info.f == pytest.approx(12.25, abs=1e-12)
         assert np.abs(s.get_u(torch.float64).cpu().numpy() - 0.5).max() == 0.0
@@ -185,17 +194,19 @@ def test_pgrad_stop_matches_the_oracle(fc):
     assert np.allclose(hist["r"][1:], ref.r[1:], rtol=1e-9)
 
 
-def test_step_calls_compose_and_are_deterministic(fc):
+@pytest.mark.parametrize("defer", [False, True])
+def test_step_calls_compose_and_are_deterministic(fc, defer):
     wl = W.er_planted(5000, 32, 15.0, 0.05, 7)
     S = wl.to("cuda")
     outs = []
     for split in ([7], [3, 4], [1, 1, 5]):
-        with fc.Solver(S.row_ptr, S.col_idx, S.val, 32, S.U0, step=1e-3) as s:
+        with fc.Solver(S.row_ptr, S.col_idx, S.val, 32, S.U0, step=1e-3, defer_loss=defer) as s:
             for k in split:
                 s.step(k)
-            outs.append((s.get_u().cpu().numpy(), s.info().f))
-    for U, f in outs[1:]:
+            outs.append((s.get_u().cpu().numpy(), s.info().f, s.history()["f"]))
+    for U, f, hf in outs[1:]:
         assert np.array_equal(U, outs[0][0]) and f == outs[0][1]
+        assert np.array_equal(hf, outs[0][2])
 
 
 def test_solve_budget_and_info(fc):
@@ -401,3 +412,61 @@ def test_medium_config_replays_backtracking_fp32(fc):
     print(f"medium replay fp32: f_rel={f_rel:.2e} df_rel={df_rel:.2e} max|dU|={du:.2e}")
     assert f_rel <= 1e-4 and df_rel <= 1e-3 and du <= 1e-4
     assert np.abs(U.sum(1) - 1).max() <= 1e-6
+
+
+
+# --------------------------------------------------------------------------
+# deferred loss evaluation
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "mixed"])
+def test_deferred_loss_follows_the_oracle_and_the_default_mode(fc, prec):
+    wl = W.chung_lu_planted(20000, 16, 20.0, 2.1, 50_000.0, 0.05, 9,
+                            val_dtype=torch.float64, u_dtype=torch.float64)
+    rp, ci, v, U0 = wl.numpy()
+    if prec != "fp64":
+        v = v.astype(np.float32).astype(np.float64)
+        U0 = U0.astype(np.float32).astype(np.float64)
+    v_ref = v.astype(np.float16).astype(np.float64) if prec == "mixed" else v
+    spec, _ = oracle.spectral_norm(rp, ci, v_ref, True)
+    tau = 20.0 / oracle.lipschitz_bound(spec, wl.n)
+    ref = oracle.solve(rp, ci, v_ref, True, U0, accelerate=True, max_iter=30, step=tau)
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, 16, prec, 30, step=tau, defer_loss=True,
+                               reorder="degree")
+    info0, U0g, hist0 = _solve_gpu(fc, rp, ci, v, U0, 16, prec, 30, step=tau, reorder="degree")
+    tol = {"fp64": 1e-9, "fp32": 1e-4, "mixed": 1e-4}[prec]
+    f_err = np.abs(hist["f"] - ref.f).max() / abs(ref.f[-1])
+    print(f"deferred {prec}: history f_rel {f_err:.2e} max|dU| {np.abs(U - ref.X).max():.2e} "
+          f"vs default mode {np.abs(U - U0g).max():.2e}")
+    assert info.iter == 30 and len(hist["f"]) == 31
+    assert f_err <= tol
+    assert np.abs(U - ref.X).max() <= {"fp64": 1e-9, "fp32": 1e-4, "mixed": 5e-3}[prec]
+    assert np.abs(U - U0g).max() <= {"fp64": 1e-12, "fp32": 1e-5, "mixed": 1e-3}[prec]
+    assert np.abs(hist["f"] - hist0["f"]).max() <= {"fp64": 1e-12, "fp32": 1e-6,
+                                                    "mixed": 1e-6}[prec] * abs(ref.f[0])
+    assert info.f == hist["f"][-1] and info.f_prev == hist["f"][-2]
+
+
+def test_deferred_loss_checkpoints_and_rules(fc):
+    wl = W.er_planted(4000, 16, 12.0, 0.05, 13).to("cuda")
+    kw = dict(step=1e-3, defer_loss=True)
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 16, wl.U0, **kw) as a:
+        a.step(21)
+        U_ref, f_ref, h_ref = a.get_u().cpu().numpy(), a.info().f, a.history()["f"]
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 16, wl.U0, **kw) as b:
+        b.step(8)
+        state = b.get_state()
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 16, None, **kw) as c:
+        c.set_state(state)
+        c.step(13)
+        assert np.array_equal(c.get_u().cpu().numpy(), U_ref) and c.info().f == f_ref
+        assert np.array_equal(c.history()["f"], h_ref)
+    from paper_2506_04045_amd import _native
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 16, None, step=1e-3) as d:
+        with pytest.raises(_native.FcError):
+            d.set_state(state)
+    with pytest.raises(_native.FcError):   # backtracking needs each trial's loss
+        fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 16, None, backtrack=True, defer_loss=True)
+    with fc.Server() as sv:                # the server evaluates every loss in its tick
+        with pytest.raises(_native.FcError):
+            sv.submit(1, wl.row_ptr, wl.col_idx, wl.val, 16, wl.U0, defer_loss=True)

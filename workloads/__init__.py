@@ -362,6 +362,47 @@ def config_mixed_full(seed: int = 0, device="cpu", n: int = 70_000_000) -> Workl
     return er_planted(n, 32, 30.0, 0.05, seed, device=device)
 
 
+def two_cluster_er(seed: int = 0, device="cpu", n1: int = 500_000, n2: int = 250_000,
+                   deg1: float = 1200.0, deg2: float = 1600.0, bridges: int = 200) -> Workload:
+    """The artificial graph of the paper's experiments (section 5): two
+    Erdos-Renyi clusters of n1 and n2 nodes with edge probabilities
+    deg1/(n1-1) and deg2/(n2-1), here as the expected number of edges drawn as
+    distinct pairs, plus `bridges` distinct edges between the clusters.
+    Similarities are the adjacency (S = A + I through the unit diagonal), the
+    start puts every node fully in the second cluster, and
+    meta["labels"] holds the ground truth (0 for the first n1 nodes)."""
+    n = n1 + n2
+    m1 = int(round(deg1 * n1 / 2.0))
+    m2 = int(round(deg2 * n2 / 2.0))
+    a1, b1 = er_pairs(n1, m1, seed, device=device)
+    a2, b2 = er_pairs(n2, m2, seed + 1, device=device)
+    g = _gen(seed, _STREAM_PLANT, device)
+    ka = torch.empty(0, dtype=torch.int64, device=device)
+    while ka.numel() < bridges:           # distinct inter-cluster pairs, first in draw order
+        x = torch.randint(0, n1, (2 * bridges,), generator=g, device=device)
+        y = torch.randint(n1, n, (2 * bridges,), generator=g, device=device)
+        cand = torch.cat([ka, x * n + y])
+        uniq, inv = torch.unique(cand, return_inverse=True)
+        first = torch.full((uniq.numel(),), cand.numel(), dtype=torch.int64, device=device)
+        first.scatter_reduce_(0, inv, torch.arange(cand.numel(), device=device), reduce="amin")
+        ka = cand[torch.sort(first).values]
+    ka = ka[:bridges]
+    keys = torch.cat([a1 * n + b1, (a2 + n1) * n + (b2 + n1), ka])
+    del a1, b1, a2, b2
+    keys = torch.sort(keys).values
+    a, b = keys // n, keys % n
+    del keys
+    v = torch.ones(a.numel(), dtype=torch.float32, device=device)
+    row_ptr, col, val = symmetric_csr(n, a, b, v)
+    del a, b, v
+    U0 = torch.zeros(n, 2, dtype=torch.float32, device=device)
+    U0[:, 1] = 1.0
+    labels = torch.cat([torch.zeros(n1, dtype=torch.int8), torch.ones(n2, dtype=torch.int8)])
+    return Workload(n, 2, row_ptr, col, val, U0,
+                    dict(pattern="two-cluster ER", n1=n1, n2=n2, deg1=deg1, deg2=deg2,
+                         bridges=bridges, labels=labels))
+
+
 def serving_request(req_id: int, device="cpu", base_seed: int = 0) -> Workload:
     """One serving request: n log-uniform in [500, 2e5], c in {4,8,16,32,64},
     average degree U(10, 40), planted communities, ER pattern."""
