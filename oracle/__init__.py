@@ -80,6 +80,7 @@ def _load():
         lib.fcref_x_s.argtypes = [i64, P, P, P, ctypes.c_int, ctypes.c_int, P, P]
         lib.fcref_share.argtypes = [i64, ctypes.c_int, P, P]
         lib.fcref_x_s_rows.argtypes = [i64, P, P, P, P, ctypes.c_int, ctypes.c_int, P, P]
+        lib.fcref_hvp.argtypes = [i64, P, P, P, ctypes.c_int, ctypes.c_int, P, P, P]
         lib.fcref_project_simplex.argtypes = [ctypes.c_int, P, P]
         lib.fcref_project_columns.argtypes = [i64, ctypes.c_int, P, P]
         lib.fcref_loss.argtypes = [i64, P, P, P, ctypes.c_int, ctypes.c_int, P]
@@ -205,6 +206,58 @@ def gradient(row_ptr, col_idx, val, diag_unit: bool, X) -> np.ndarray:
     _load().fcref_gradient(n, _ptr(rp), _ptr(ci), _ptr(v), int(diag_unit), X.shape[1],
                            _ptr(X), _ptr(out))
     return out
+
+
+def hvp(row_ptr, col_idx, val, diag_unit: bool, X, V) -> np.ndarray:
+    """Hessian of f at X applied to V (Theorem 4.1, eq. hessian), rows as X."""
+    n, rp, ci, v = _csr(row_ptr, col_idx, val)
+    X = _mat(X, n)
+    V = _mat(V, n)
+    if V.shape != X.shape:
+        raise ValueError("V must have the shape of X")
+    out = np.empty_like(X)
+    _load().fcref_hvp(n, _ptr(rp), _ptr(ci), _ptr(v), int(diag_unit), X.shape[1], _ptr(X),
+                      _ptr(V), _ptr(out))
+    return out
+
+
+def face_basis(X, zero_tol: float = 0.0) -> np.ndarray:
+    """Orthonormal basis (columns, flattened in the layout of X) of the
+    directions V whose rows sum to zero and vanish where x_ki <= zero_tol:
+    the tangent directions of Omega at X (eq. 1st_tangent_cone) that keep
+    every zero component at zero.  They satisfy <grad f(X), V> = 0 at a
+    critical point, so Theorem 4.1 asks <Hess f(X) V, V> >= 0 on them."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    n, C = X.shape
+    cols = []
+    for i in range(n):
+        sup = np.flatnonzero(X[i] > zero_tol)
+        m = sup.size
+        for t in range(1, m):            # Helmert contrasts on the support
+            w = np.zeros(C)
+            w[sup[:t]] = 1.0 / t
+            w[sup[t]] = -1.0
+            w /= np.linalg.norm(w)
+            col = np.zeros(n * C)
+            col[i * C:(i + 1) * C] = w
+            cols.append(col)
+    return np.array(cols).T if cols else np.zeros((n * C, 0))
+
+
+def curvature_dense(row_ptr, col_idx, val, diag_unit: bool, X, zero_tol: float = 0.0):
+    """Smallest eigenvalue of the Hessian restricted to face_basis(X), and a
+    unit eigen-direction (layout of X), from the dense restricted matrix
+    B^T H B built column by column with hvp (small instances only)."""
+    X = np.ascontiguousarray(X, dtype=np.float64)
+    B = face_basis(X, zero_tol)
+    if B.shape[1] == 0:
+        return float("inf"), np.zeros_like(X)
+    HB = np.stack([hvp(row_ptr, col_idx, val, diag_unit, X, B[:, j].reshape(X.shape)).ravel()
+                   for j in range(B.shape[1])], axis=1)
+    K = B.T @ HB
+    K = 0.5 * (K + K.T)
+    w, Q = np.linalg.eigh(K)
+    return float(w[0]), (B @ Q[:, 0]).reshape(X.shape)
 
 
 def spectral_norm(row_ptr, col_idx, val, diag_unit: bool, max_iter: int = 1000,

@@ -248,6 +248,45 @@ void fcref_gradient(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
     free(share);
 }
 
+/* The Hessian of f at X applied to a direction V, eq. (hessian) of
+ * Theorem 4.1: -4 V (S - X^T X) + 4 X (V^T X + X^T V).  Column i of it is
+ *   -4 (V s_i - sum_j v_j (x_j . x_i)) + 4 sum_j x_j ((v_j . x_i) + (x_j . v_i)),
+ * which with share = X X^T and cross = X V^T (both C x C) is
+ *   -4 V s_i + 4 (cross^T + cross) x_i + 4 share v_i
+ * (the term V X^T x_i = cross^T x_i).  X, V and the result HV share the
+ * layout of X. */
+void fcref_hvp(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+               const double *val, int diag_unit, int C, const double *X,
+               const double *V, double *HV)
+{
+    double *VS = (double *)malloc(sizeof(double) * (size_t)n * C);
+    double *share = (double *)malloc(sizeof(double) * (size_t)C * C);
+    double *cross = (double *)calloc((size_t)C * C, sizeof(double));
+    fcref_x_s(n, row_ptr, col_idx, val, diag_unit, C, V, VS);
+    fcref_share(n, C, X, share);
+    for (int64_t j = 0; j < n; ++j) {          /* cross = sum_j x_j v_j^T */
+        const double *xj = X + j * C, *vj = V + j * C;
+        for (int k = 0; k < C; ++k)
+            for (int l = 0; l < C; ++l)
+                cross[k * C + l] += xj[k] * vj[l];
+    }
+    #pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; ++i) {
+        const double *xi = X + i * C, *vi = V + i * C;
+        for (int k = 0; k < C; ++k) {
+            double a = 0.0, b = 0.0;
+            for (int l = 0; l < C; ++l) {
+                a += (cross[l * C + k] + cross[k * C + l]) * xi[l];
+                b += share[k * C + l] * vi[l];
+            }
+            HV[i * C + k] = -4.0 * VS[i * C + k] + 4.0 * a + 4.0 * b;
+        }
+    }
+    free(VS);
+    free(share);
+    free(cross);
+}
+
 /* Spectral norm ||S||_2 of the (symmetric, nonnegative) similarity in use, by
  * power iteration from the normalised all-ones vector: v <- S v / ||S v||,
  * estimate ||S v||.  Stops when the estimate changes by less than rtol

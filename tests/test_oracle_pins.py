@@ -483,3 +483,66 @@ def test_node_and_label_permutation_equivariance(O):
     q = rng.permutation(c)
     perm_labels = O.solve(rp, ci, v, True, X0[:, q], accelerate=True, max_iter=30, step=1e-3)
     assert np.abs(perm_labels.X - base.X[:, q]).max() <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# second order (Theorem 4.1): Hessian-vector products and curvature on the face
+# --------------------------------------------------------------------------
+
+def _quadratic_form_by_definition(S, X, V, h=0.25):
+    """<V, Hess f(X) V> = 2 a2, where f(X + eps V) = a0 + ... + a4 eps^4 is a
+    quartic in eps: five samples of the double-sum objective fix it exactly."""
+    eps = np.array([-2.0, -1.0, 0.0, 1.0, 2.0]) * h
+    vals = [pins.objective_by_definition(S, X + e * V) for e in eps]
+    coef = np.linalg.solve(np.vander(eps, 5, increasing=True), vals)
+    return 2.0 * coef[2]
+
+
+@pytest.mark.parametrize("diag_unit", [False, True])
+def test_hvp_matches_the_objective_by_definition(O, diag_unit):
+    rng = np.random.default_rng(31)
+    n, c = 8, 3
+    (rp, ci, v), A = pins.random_symmetric_csr(n, 0.5, rng)
+    S = A + (np.eye(n) if diag_unit else 0)
+    X = pins.random_simplex_rows(n, c, rng)
+    V = rng.normal(size=(n, c))
+    HV = O.hvp(rp, ci, v, diag_unit, X, V)
+    q = _quadratic_form_by_definition(S, X, V)
+    assert float((V * HV).sum()) == pytest.approx(q, rel=1e-9)
+    for _ in range(3):     # every component, through polarization
+        W = rng.normal(size=(n, c))
+        pol = 0.25 * (_quadratic_form_by_definition(S, X, V + W)
+                       - _quadratic_form_by_definition(S, X, V - W))
+        assert float((W * HV).sum()) == pytest.approx(pol, rel=1e-8, abs=1e-9)
+        HW = O.hvp(rp, ci, v, diag_unit, X, W)
+        assert float((W * HV).sum()) == pytest.approx(float((V * HW).sum()), rel=1e-12)
+
+
+def test_example41_hessian_form_and_negative_curvature(O, ex41):
+    (rp, ci, v), _ = ex41_csr(ex41, "stored")
+    X3 = np.array(ex41["scenario3"]["X"]).T
+    V = np.array(ex41["hessian_check"]["V"], dtype=float).T
+    HV = O.hvp(rp, ci, v, False, X3, V)
+    assert float((V * HV).sum()) == pytest.approx(ex41["hessian_check"]["hessian_quadratic_form"],
+                                                  abs=1e-12)
+    lam, D = O.curvature_dense(rp, ci, v, False, X3)
+    assert lam <= -4.0 / float((V * V).sum()) + 1e-12     # Rayleigh quotient bound
+    assert np.abs(D.sum(1)).max() <= 1e-12 and abs(np.linalg.norm(D) - 1) <= 1e-12
+    assert float((D * O.hvp(rp, ci, v, False, X3, D)).sum()) == pytest.approx(lam, abs=1e-10)
+
+
+def test_planted_minimizer_has_no_negative_curvature(O):
+    rng = np.random.default_rng(5)
+    n, c = 12, 3
+    Ustar = pins.random_simplex_rows(n, c, rng)
+    S = Ustar @ Ustar.T
+    rp, ci, v = pins.csr_from_dense(S)
+    lam, _ = O.curvature_dense(rp, ci, v, False, Ustar)
+    assert lam >= -1e-10
+    # a face point with zero components: the basis keeps them at zero
+    Z = Ustar.copy()
+    Z[0] = [1.0, 0.0, 0.0]
+    B = O.face_basis(Z)
+    assert B.shape[1] == n * (c - 1) - 2
+    assert np.abs(B.T @ B - np.eye(B.shape[1])).max() <= 1e-12
+    assert np.abs(B[1:3, :]).max() == 0.0
