@@ -350,6 +350,41 @@ fc_status fc_server_stats(fc_server *sv, int32_t *n_pending, int32_t *n_active,
 /* Stop the worker and free everything, including unreleased results. */
 void fc_server_destroy(fc_server *sv);
 
+/* ------------------------------------------------------------------------
+ * Second-order check (section 4, Theorem 4.1)
+ * ---------------------------------------------------------------------- */
+
+/* HV = Hess f(U) V, eq. (hessian) of Theorem 4.1 in the row layout:
+ *   row i of HV = -4 (S_eff V)_i + 4 v_i (U^T U) + 4 u_i (U^T V + V^T U).
+ * S as for fc_create (values FC_F64 with dtype FC_F64, or FC_F32 with
+ * FC_F32); U, V, HV: device, n x c row-major of dtype (HV must not alias U
+ * or V).  The sparse product and the c x c products U^T U, U^T V run on the
+ * GPU (matrix cores for the latter); the row combination is in double.
+ * Synchronises the stream before returning.  Errors: FC_ERR_INVALID_ARG. */
+fc_status fc_hessian_vector(const fc_csr *S, fc_diag diag, const void *U, const void *V, void *HV,
+                            fc_dtype dtype, int32_t c, void *stream);
+
+/* Smallest curvature of f at U over the face directions
+ *   K(U) = { V : every row of V sums to 0, v_ik = 0 where u_ik <= zero_tol },
+ * the tangent directions of Omega at U (the cone in the proof of Theorem 4.1)
+ * that keep each zero component at zero; at a critical point they satisfy
+ * <grad f(U), V> = 0, so Theorem 4.1 requires <Hess f(U) V, V> >= 0 on K(U)
+ * for a local minimiser.  Lanczos on the Hessian restricted to K(U), started
+ * from the projection of V0 (device, n x c, caller-chosen, e.g. random),
+ * with full reorthogonalisation (two Gram-Schmidt passes per step) for
+ * `krylov` steps (1..512) or until an invariant subspace is reached; the
+ * Ritz pair with the smallest value of the small tridiagonal matrix (cyclic
+ * Jacobi) gives *lambda_min and, if V_out (device, n x c) is non-NULL, the
+ * unit-norm Ritz direction.  *lambda_min < 0 certifies that U is not a local
+ * minimiser (V_out is a direction of negative curvature); a value >= 0 is
+ * evidence, not proof, of the converse.  *steps (may be NULL) receives the
+ * number of Lanczos steps.  The Krylov basis takes (krylov + 1) n c' words
+ * (c' = padded c): FC_ERR_OUT_OF_MEMORY when it would not fit.  dtype and S
+ * as for fc_hessian_vector.  Synchronises the stream. */
+fc_status fc_curvature(const fc_csr *S, fc_diag diag, const void *U, const void *V0, fc_dtype dtype,
+                       int32_t c, int32_t krylov, double zero_tol, double *lambda_min, void *V_out,
+                       int32_t *steps, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -371,3 +371,37 @@ def spectral_norm(row_ptr, col_idx, val, diag: str = "unit", max_iter: int = 100
                                       float(rtol), _stream_ptr(stream), ctypes.byref(out),
                                       ctypes.byref(it)))
     return float(out.value), int(it.value)
+
+
+def hessian_vector(row_ptr, col_idx, val, U: torch.Tensor, V: torch.Tensor, diag: str = "unit",
+                   stream=None) -> torch.Tensor:
+    """Hess f(U) V, Theorem 4.1 eq. (hessian) (fc_hessian_vector)."""
+    csr = _CsrView(row_ptr, col_idx, val)
+    U = _dev(U, "U", (torch.float64, torch.float32))
+    V = _dev(V, "V", (U.dtype,))
+    if V.shape != U.shape:
+        raise ValueError("V must have the shape of U")
+    HV = torch.empty_like(U)
+    N.check(N.load().fc_hessian_vector(ctypes.byref(csr.c), _DIAG[diag], U.data_ptr(), V.data_ptr(),
+                                       HV.data_ptr(), _DT[U.dtype], U.shape[1], _stream_ptr(stream)))
+    return HV
+
+
+def curvature(row_ptr, col_idx, val, U: torch.Tensor, V0: torch.Tensor, krylov: int = 40,
+              diag: str = "unit", zero_tol: float = 0.0, stream=None):
+    """(lambda_min, V, steps): smallest curvature of f at U over the face
+    directions and its Ritz direction (fc_curvature)."""
+    csr = _CsrView(row_ptr, col_idx, val)
+    U = _dev(U, "U", (torch.float64, torch.float32))
+    V0 = _dev(V0, "V0", (U.dtype,))
+    if V0.shape != U.shape:
+        raise ValueError("V0 must have the shape of U")
+    V = torch.empty_like(U)
+    lam = ctypes.c_double(0.0)
+    steps = ctypes.c_int32(0)
+    N.check(N.load().fc_curvature(ctypes.byref(csr.c), _DIAG[diag], U.data_ptr(), V0.data_ptr(),
+                                  _DT[U.dtype], U.shape[1], int(krylov), float(zero_tol),
+                                  ctypes.byref(lam), V.data_ptr(), ctypes.byref(steps),
+                                  _stream_ptr(stream)))
+    return float(lam.value), V, int(steps.value)
+

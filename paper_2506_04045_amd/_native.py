@@ -31,7 +31,7 @@ EXPORTED = [
     "fc_gram", "fc_spectral_norm", "fc_last_error",
     "fc_server_opts_default", "fc_server_clock", "fc_server_create", "fc_server_submit",
     "fc_server_poll", "fc_server_get_u", "fc_server_release", "fc_server_stats",
-    "fc_server_destroy",
+    "fc_server_destroy", "fc_hessian_vector", "fc_curvature",
 ]
 
 
@@ -152,6 +152,13 @@ def load() -> ctypes.CDLL:
     lib.fc_server_stats.restype = st
     lib.fc_server_destroy.argtypes = [P]
     lib.fc_server_destroy.restype = None
+    lib.fc_hessian_vector.argtypes = [ctypes.POINTER(CSR), ctypes.c_int, P, P, P, ctypes.c_int,
+                                      i32, P]
+    lib.fc_hessian_vector.restype = st
+    lib.fc_curvature.argtypes = [ctypes.POINTER(CSR), ctypes.c_int, P, P, ctypes.c_int, i32, i32,
+                                 f64, ctypes.POINTER(ctypes.c_double), P,
+                                 ctypes.POINTER(ctypes.c_int32), P]
+    lib.fc_curvature.restype = st
     _lib = lib
     return lib
 

@@ -33,6 +33,7 @@
 
 #include "fc.h"
 #include "fc_kernels.hpp"
+#include "fc_second.hpp"
 
 using namespace fc;
 
@@ -1628,3 +1629,4 @@ fc_status fc_spectral_norm(const fc_csr *S, fc_diag diag, int32_t max_iter, doub
 }  // extern "C"
 
 #include "fc_server.inc"
+#include "fc_second.inc"
