@@ -14,9 +14,9 @@
  *   torch CUDA tensor's data_ptr()).  Pointers named "host" are host memory.
  * - `stream` is a hipStream_t passed as void*; NULL means the default stream.
  *   All device work is enqueued on that stream.  Calls that return scalars
- *   (fc_step, fc_solve, fc_objective, fc_gram, fc_spectral_norm, fc_create)
- *   synchronise that stream before returning; fc_project, fc_spmm and
- *   fc_get_u only enqueue work.
+ *   (fc_step, fc_solve, fc_objective, fc_gram, fc_spectral_norm, fc_create,
+ *   fc_curvature) and fc_hessian_vector synchronise that stream before
+ *   returning; fc_project, fc_spmm and fc_get_u only enqueue work.
  * - S is borrowed: the caller keeps its arrays alive and unmodified until
  *   fc_destroy of every solver built on it.  U0 is copied at fc_create.
  *   Output buffers are caller-allocated.
