@@ -300,6 +300,8 @@ def main() -> int:
     ap.add_argument("--precision", choices=["fp32", "mixed"], default="fp32")
     ap.add_argument("--reorder", choices=["none", "degree"], default="degree",
                     help="internal renumbering of the articles (set up in fc_create, untimed)")
+    ap.add_argument("--backtrack", action="store_true",
+                    help="Beck-Teboulle backtracking (L0 = L_thm/100) instead of the constant step")
     ap.add_argument("--defer-loss", type=int, default=1,
                     help="1: each iterate's loss is formed during the next pass (fc_options.defer_loss)")
     ap.add_argument("--no-artificial", action="store_true",
@@ -372,13 +374,15 @@ def main() -> int:
 
     prec = args.precision
     t0 = time.perf_counter()
+    defer = bool(args.defer_loss) and not args.backtrack
     solver = fc.Solver(wl.row_ptr, wl.col_idx, wl.val, args.c, wl.U0, precision=prec,
-                       accelerate=True, step=0.0, reorder=args.reorder,
-                       defer_loss=bool(args.defer_loss))
+                       accelerate=True, step=0.0, backtrack=args.backtrack, reorder=args.reorder,
+                       defer_loss=defer)
     torch.cuda.synchronize()
     log(f"solver created in {time.perf_counter() - t0:.1f} s")
 
     info = solver.step(args.warmup)
+    trials0 = info.trials
     log(f"warmup {args.warmup} iterations done, f={info.f:.6e}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -389,6 +393,7 @@ def main() -> int:
     hist = solver.history()
     f0, f_end = float(hist["f"][0]), float(info.f)
     tau = float(hist["tau"][1])
+    trials_per_iter = (info.trials - trials0) / max(1, args.steps)
     solver.close()
 
     n, c, nnz = wl.n, args.c, wl.nnz
@@ -403,7 +408,7 @@ def main() -> int:
     kernels["reduce"] = {"avg_ms": avg["reduce"]}
     kernels["control"] = {"avg_ms": avg["control"]}
     dom = max(("spmm", "fused"), key=lambda k: avg[k])
-    wkey = f"powerlaw_n{n}_c{c}_{prec}_{args.reorder}" + ("_deferred" if args.defer_loss else "")
+    wkey = f"powerlaw_n{n}_c{c}_{prec}_{args.reorder}" + ("_deferred" if defer else "")
     traffic = measured_traffic(dom, wkey)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["achieved_GBps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -442,12 +447,14 @@ def main() -> int:
         "config": {
             "workload": (f"power-law fuzzy clustering n={n:,} c={c}: Chung-Lu pattern "
                          f"(exponent 2.1, mean degree 20, max 50,000), {nnz:,} stored nnz, "
-                         f"planted communities sigma 0.05, unit diagonal, FISTA constant step "
-                         f"1/L (Theorem 3.1), {prec}, articles relabelled: {args.reorder}, "
-                         f"loss evaluation deferred: {bool(args.defer_loss)}"),
+                         f"planted communities sigma 0.05, unit diagonal, FISTA "
+                         + ("with backtracking (L0 = L_thm/100, eta 2)" if args.backtrack else
+                            "constant step 1/L (Theorem 3.1)")
+                         + f", {prec}, articles relabelled: {args.reorder}, "
+                         f"loss evaluation deferred: {defer}"),
             "n": n, "c": c, "nnz": nnz, "precision": prec, "reorder": args.reorder,
-            "defer_loss": bool(args.defer_loss), "tau": tau,
-            "f0": f0, "f_end": f_end,
+            "defer_loss": defer, "backtrack": bool(args.backtrack), "tau": tau,
+            "trials_per_iteration": trials_per_iter, "f0": f0, "f_end": f_end,
         },
         "kernels": kernels,
         "roofline": roofline,
