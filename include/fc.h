@@ -322,8 +322,11 @@ void fc_server_opts_default(fc_server_opts *opts);
 double fc_server_clock(void);
 
 /* Start a server on the device current in the calling thread; `stream`
- * (hipStream_t on that device, NULL = a new stream) carries the batched
- * ticks.  Errors: FC_ERR_INVALID_ARG, FC_ERR_DEVICE. */
+ * (hipStream_t on that device, NULL = a new stream) carries the batch tables,
+ * the state polls and, with use_graph, the captured ticks; without use_graph
+ * each group of requests (padded c, step rule) ticks on a stream of its own
+ * so that the groups' kernels overlap.  Errors: FC_ERR_INVALID_ARG,
+ * FC_ERR_DEVICE. */
 fc_status fc_server_create(const fc_server_opts *opts, void *stream, fc_server **out);
 
 /* Queue one solve.  S (device CSR, FC_F32 values) and U0 (device n x c,
