@@ -1046,7 +1046,7 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
                 gA[a][s] = GYs[(16 * a + r) * CPM + kslot<T>(s, g)];
     }
 
-    __shared__ T lds[NMAT][64 * STRIDE];
+    __shared__ __attribute__((aligned(16))) T lds[NMAT][64 * STRIDE];
 
     double sc_try = 0.0, sc_lin = 0.0, sc_sq = 0.0, sc_corr = 0.0, sc_trc = 0.0;
     int32_t n_bad = 0;   // non-finite step values
@@ -1181,16 +1181,18 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
             if (g == 0 && live)
                 sc_corr += ysum * dsum;
         }
-        // new iterate (and its bfloat16 copy for the next sparse product)
+        // the bfloat16 copy of the new iterate for the next sparse product (with
+        // the new iterate itself, written here in this mode)
+        if constexpr (SHADOW) {
 #pragma unroll
-        for (int a = 0; a < M; ++a) {
+            for (int a = 0; a < M; ++a) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int k = kslot<T>(4 * a + q, g);
-                if (live && k < CP) {
-                    Xn[row * CP + k] = p[4 * a + q];
-                    if (SHADOW)
+                for (int q = 0; q < 4; ++q) {
+                    const int k = kslot<T>(4 * a + q, g);
+                    if (live && k < CP) {
+                        Xn[row * CP + k] = p[4 * a + q];
                         shadow[row * CP + k] = __float2bfloat16((float)p[4 * a + q]);
+                    }
                 }
             }
         }
@@ -1209,6 +1211,24 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
             }
         }
         __syncthreads();
+        // the new iterate: a wave's 16 rows are contiguous in memory, so they are
+        // written from the staged tile in 16-byte pieces, consecutive lanes on
+        // consecutive pieces (a lane's own slots are 4 components of 16 rows)
+        if constexpr (!SHADOW) {
+            constexpr int PER = 16 / (int)sizeof(T);   // components per piece
+            constexpr int RP = CP / PER;               // pieces per row
+            constexpr int PIECES = 16 * RP;            // pieces of a wave's rows
+            using V16 = T __attribute__((ext_vector_type(PER)));
+            const int64_t row0 = wt * 64 + wave * 16;
+#pragma unroll
+            for (int e0 = 0; e0 < PIECES; e0 += 64) {
+                const int e = e0 + lane;
+                const int lr = e / RP, kc = (e % RP) * PER;
+                if ((PIECES % 64 == 0 || e < PIECES) && row0 + lr < n)
+                    *reinterpret_cast<V16 *>(Xn + (row0 + lr) * CP + kc) =
+                        *reinterpret_cast<const V16 *>(&lds[0][(wave * 16 + lr) * STRIDE + kc]);
+            }
+        }
 #pragma unroll
         for (int kk = 0; kk < BPW; ++kk) {
             const int kb = wave + 4 * kk;
