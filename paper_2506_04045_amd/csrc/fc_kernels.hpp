@@ -714,6 +714,8 @@ __device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, 
                     chunk_sum[k * CP + sub * NE + q] = acc[q];
         }
     }
+    if (plain)   // no loss terms: the products of a deferred instance write no partials
+        return;
     __shared__ double sh[256];
     sh[tid] = trace_acc;
     __syncthreads();
@@ -780,6 +782,8 @@ __device__ __forceinline__ void combine_body(const Inst &I, int role, int64_t bl
             }
         }
     }
+    if (I.defer)
+        return;
     sh[tid] = trace_acc;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
@@ -1383,8 +1387,10 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
     if (mode == 1 && !st->active)
         return;
     // the products' terms sum_i <x_i, (S X)_i>: workgroup partials of the
-    // sparse product, combined in a fixed order
-    {
+    // sparse product, combined in a fixed order (a deferred instance forms
+    // them in the fused pass instead; its products write no partials)
+    double tr_total = 0.0;
+    if (!I.defer) {
         const int64_t np = (int64_t)I.g_spmm + I.g_comb;
         double a = 0.0;
         for (int64_t q = tid; q < np; q += 256)
@@ -1396,9 +1402,9 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
                 sh[tid] += sh[tid + s];
             __syncthreads();
         }
+        tr_total = sh[0];
+        __syncthreads();
     }
-    const double tr_total = sh[0];
-    __syncthreads();
     const int c = st->c;
     const double *Gp = red_mats;                       // Gram of the new point
     const double *Gnext = red_mats + (mode == 1 && st->accelerate ? L::MAT : 0);
