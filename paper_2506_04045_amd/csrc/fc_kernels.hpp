@@ -1185,21 +1185,6 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
             if (g == 0 && live)
                 sc_corr += ysum * dsum;
         }
-        // the bfloat16 copy of the new iterate for the next sparse product (with
-        // the new iterate itself, written here in this mode)
-        if constexpr (SHADOW) {
-#pragma unroll
-            for (int a = 0; a < M; ++a) {
-#pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    const int k = kslot<T>(4 * a + q, g);
-                    if (live && k < CP) {
-                        Xn[row * CP + k] = p[4 * a + q];
-                        shadow[row * CP + k] = __float2bfloat16((float)p[4 * a + q]);
-                    }
-                }
-            }
-        }
         // stage the tile for the Gram products
         __syncthreads();
         const int lrow = wave * 16 + r;
@@ -1215,10 +1200,11 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
             }
         }
         __syncthreads();
-        // the new iterate: a wave's 16 rows are contiguous in memory, so they are
-        // written from the staged tile in 16-byte pieces, consecutive lanes on
+        // the new iterate (and its bfloat16 copy for the next sparse product): a
+        // wave's 16 rows are contiguous in memory, so they are written from the
+        // staged tile in pieces of up to 16 bytes, consecutive lanes on
         // consecutive pieces (a lane's own slots are 4 components of 16 rows)
-        if constexpr (!SHADOW) {
+        {
             constexpr int PER = 16 / (int)sizeof(T);   // components per piece
             constexpr int RP = CP / PER;               // pieces per row
             constexpr int PIECES = 16 * RP;            // pieces of a wave's rows
@@ -1231,6 +1217,26 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
                 if ((PIECES % 64 == 0 || e < PIECES) && row0 + lr < n)
                     *reinterpret_cast<V16 *>(Xn + (row0 + lr) * CP + kc) =
                         *reinterpret_cast<const V16 *>(&lds[0][(wave * 16 + lr) * STRIDE + kc]);
+            }
+            if constexpr (SHADOW) {
+                constexpr int SPER = CP < 8 ? CP : 8;      // bfloat16 components per piece
+                constexpr int SRP = CP / SPER;
+                constexpr int SPIECES = 16 * SRP;
+                using W = uint32_t __attribute__((ext_vector_type(SPER / 2)));
+#pragma unroll
+                for (int e0 = 0; e0 < SPIECES; e0 += 64) {
+                    const int e = e0 + lane;
+                    const int lr = e / SRP, kc = (e % SRP) * SPER;
+                    if ((SPIECES % 64 == 0 || e < SPIECES) && row0 + lr < n) {
+                        const T *src = &lds[0][(wave * 16 + lr) * STRIDE + kc];
+                        W w;
+#pragma unroll
+                        for (int h = 0; h < SPER / 2; ++h)
+                            w[h] = (uint32_t)__bfloat16_as_ushort(__float2bfloat16((float)src[2 * h])) |
+                                   ((uint32_t)__bfloat16_as_ushort(__float2bfloat16((float)src[2 * h + 1])) << 16);
+                        *reinterpret_cast<W *>(shadow + (row0 + lr) * CP + kc) = w;
+                    }
+                }
             }
         }
 #pragma unroll
