@@ -133,8 +133,30 @@ def serve_bench(args) -> dict:
         f_seq.append(info.f)
     mu_seq = R / sum(service)
     log(f"serving: sequential {mu_seq:.1f} solves/s")
-    out = {"requests": R, "slots": args.serve_slots, "ticks_per_poll": args.serve_ticks,
-           "graph": bool(args.serve_graph),
+    sched = dict(ticks_per_poll=args.serve_ticks, use_graph=bool(args.serve_graph),
+                 grid_fused=None, grid_spmm=None)
+    tuning = None
+    if args.serve_tune > 0:
+        # the autotuner runs on its own sample of the same mix (request ids
+        # disjoint from the measured trace), before and outside the timed runs
+        sample = [W.serving_request(100_000 + i, device="cuda") for i in range(args.serve_tune)]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tuned = fc.tune_server([dict(row_ptr=w.row_ptr, col_idx=w.col_idx, val=w.val, c=w.c,
+                                     U0=w.U0, **SERVE_SOLVE) for w in sample],
+                               max_active=args.serve_slots, hbm_budget=args.serve_budget_gb * 2**30,
+                               ticks_per_poll=args.serve_ticks, use_graph=bool(args.serve_graph))
+        sched = {k: tuned[k] for k in ("ticks_per_poll", "use_graph", "grid_fused", "grid_spmm")}
+        tuning = {"sample_requests": args.serve_tune, "server_runs": tuned["runs"],
+                  "seconds": time.perf_counter() - t0,
+                  "sample_solves_per_s": tuned["solves_per_s"]}
+        del sample
+        log(f"serving: tuned schedule {sched} ({tuned['runs']} runs, "
+            f"{tuning['seconds']:.1f} s, sample at {tuned['solves_per_s']:.1f} solves/s)")
+    out = {"requests": R, "slots": args.serve_slots, "ticks_per_poll": sched["ticks_per_poll"],
+           "graph": bool(sched["use_graph"]), "launch_table": {"grid_fused": sched["grid_fused"],
+                                                             "grid_spmm": sched["grid_spmm"]},
+           "autotuner": tuning,
            "sequential_fp32": {"solves_per_s": mu_seq}, "loads": []}
     for li, load in enumerate(float(x) for x in str(args.serve_load).split(",")):
         lam = load * mu_seq
@@ -147,7 +169,7 @@ def serve_bench(args) -> dict:
         lat_seq = np.asarray(fin) - arrivals
         done = {}
         with fc.Server(max_active=args.serve_slots, hbm_budget=args.serve_budget_gb * 2**30,
-                       ticks_per_poll=args.serve_ticks, use_graph=bool(args.serve_graph)) as sv:
+                       **sched) as sv:
             t_start = fc.Server.clock()
             k = 0
             while len(done) < R:
@@ -324,6 +346,9 @@ def main() -> int:
                     help="batched iterations the serving worker launches between state polls")
     ap.add_argument("--serve-graph", type=int, default=0,
                     help="1: replay each tick as a captured hipGraph")
+    ap.add_argument("--serve-tune", type=int, default=64,
+                    help="sample requests for the serving autotuner (0: no tuning; the "
+                         "--serve-ticks / --serve-graph schedule and the built-in launch table)")
     ap.add_argument("--serve-timeout", type=float, default=600.0)
     ap.add_argument("--calibrate-copy-mb", type=int, default=0,
                     help="only run a plain elementwise copy of this many MiB (read + write), "

@@ -306,6 +306,15 @@ typedef struct {
     int32_t ticks_per_poll; /* trials launched between reads of the request states
                                (default 8) */
     int32_t use_graph;      /* 1: replay each tick from a captured hipGraph (default) */
+    /* Launch table of the batched kernels, indexed by padded width (0..4 for
+       4, 8, 16, 32, 64 columns): persistent workgroups per compute unit that
+       walk the (instance, block) tables of the fused kernel (grid_fused) and
+       of the sparse product (grid_spmm); 0 = built-in (2 and 8), otherwise
+       1..64.  Every table entry does the same work whichever workgroup takes
+       it, so these choices change the speed and never a result;
+       fc_server_tune measures them. */
+    int32_t grid_fused[5];
+    int32_t grid_spmm[5];
 } fc_server_opts;
 
 typedef struct {
@@ -353,6 +362,28 @@ fc_status fc_server_stats(fc_server *sv, int32_t *n_pending, int32_t *n_active,
 
 /* Stop the worker and free everything, including unreleased results. */
 void fc_server_destroy(fc_server *sv);
+
+/* Autotuner of the serving schedule.  Solves the n_req sample requests
+ * (S[i], opt[i], U0[i]; U0 may be NULL, or hold NULL entries, for the 1/c
+ * start; the same rules as fc_server_submit) through servers created from
+ * *base with candidate schedules and keeps the fastest, by coordinate
+ * search: first graph replay (off, on) x ticks_per_poll (4, 8, 16, 32) on
+ * all requests, then for each padded width present in the sample
+ * grid_fused (1, 2, 4) and grid_spmm (4, 8, 16, 32) on that width's
+ * requests alone.  A candidate's time runs from the first submission to the
+ * last result (set-up included), all requests submitted at once.  Every run
+ * must return, for every request, the same status, iteration and trial
+ * counts and bitwise the same final loss as the first run; otherwise
+ * FC_ERR_DEVICE.  On FC_OK *best holds *base with the chosen schedule,
+ * *solves_per_s the rate of a final run of all requests with it, and
+ * *n_runs (may be NULL) the number of server runs made.  Blocks until done;
+ * every request's memory is released before it returns.  Errors: those of
+ * the fc_server_* calls, FC_ERR_INVALID_ARG for n_req < 1 or missing
+ * arrays. */
+fc_status fc_server_tune(const fc_server_opts *base, int32_t n_req, const fc_csr *S,
+                         const fc_options *opt, const void *const *U0, fc_dtype u0_dtype,
+                         void *stream, fc_server_opts *best, double *solves_per_s,
+                         int32_t *n_runs);
 
 /* ------------------------------------------------------------------------
  * Second-order check (section 4, Theorem 4.1)

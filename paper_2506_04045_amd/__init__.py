@@ -237,18 +237,79 @@ class Result:
     t_finish: float
 
 
+def _server_options(max_active, hbm_budget, ticks_per_poll, use_graph, grid_fused=None,
+                    grid_spmm=None) -> N.ServerOpts:
+    o = N.default_server_options()
+    o.max_active = int(max_active)
+    o.hbm_budget = float(hbm_budget)
+    o.ticks_per_poll = int(ticks_per_poll)
+    o.use_graph = int(bool(use_graph))
+    for name, vals in (("grid_fused", grid_fused), ("grid_spmm", grid_spmm)):
+        if vals is not None:
+            vals = [int(v) for v in vals]
+            if len(vals) != 5:
+                raise ValueError(f"{name} needs 5 entries (padded widths 4, 8, 16, 32, 64)")
+            getattr(o, name)[:] = vals
+    return o
+
+
+def tune_server(requests, max_active: int = 64, hbm_budget: float = 32.0 * 2**30,
+                ticks_per_poll: int = 8, use_graph: bool = True, stream=None) -> dict:
+    """fc_server_tune on sample requests, each a dict with row_ptr, col_idx,
+    val, c, U0 (or None) and solver options as Solver takes them.  Returns
+    the chosen schedule (ticks_per_poll, use_graph, grid_fused, grid_spmm:
+    keyword arguments of Server), the rate of the final run and the number
+    of server runs."""
+    lib = N.load()
+    base = _server_options(max_active, hbm_budget, ticks_per_poll, use_graph)
+    k = len(requests)
+    if k < 1:
+        raise ValueError("tune_server needs at least one request")
+    views, keep = [], []
+    csrs = (N.CSR * k)()
+    opts = (N.Options * k)()
+    u0s = (ctypes.c_void_p * k)()
+    u0_dt = None
+    for i, r in enumerate(requests):
+        v = _CsrView(r["row_ptr"], r["col_idx"], r["val"])
+        views.append(v)
+        csrs[i] = v.c
+        extra = {key: val for key, val in r.items()
+                 if key not in ("row_ptr", "col_idx", "val", "c", "U0")}
+        opts[i] = _options(int(r["c"]), **extra)
+        U0 = r.get("U0")
+        if U0 is not None:
+            U0 = _dev(U0, "U0", (torch.float64, torch.float32))
+            keep.append(U0)
+            if u0_dt is not None and _DT[U0.dtype] != u0_dt:
+                raise ValueError("all sample starts must have one dtype")
+            u0_dt = _DT[U0.dtype]
+            u0s[i] = U0.data_ptr()
+    best = N.ServerOpts()
+    rate = ctypes.c_double(0.0)
+    runs = ctypes.c_int32(0)
+    N.check(lib.fc_server_tune(ctypes.byref(base), k, csrs, opts, u0s,
+                               N.FC_F32 if u0_dt is None else u0_dt,
+                               None if stream is None else int(stream.cuda_stream),
+                               ctypes.byref(best), ctypes.byref(rate), ctypes.byref(runs)))
+    return dict(ticks_per_poll=int(best.ticks_per_poll), use_graph=bool(best.use_graph),
+                grid_fused=list(best.grid_fused), grid_spmm=list(best.grid_spmm),
+                solves_per_s=float(rate.value), runs=int(runs.value))
+
+
 class Server:
     """Continuous-batching server (fc_server_*).  Submitted tensors are
     borrowed until the request is released."""
 
     def __init__(self, max_active: int = 64, hbm_budget: float = 32.0 * 2**30,
-                 ticks_per_poll: int = 8, use_graph: bool = True, stream=None):
+                 ticks_per_poll: int = 8, use_graph: bool = True, grid_fused=None,
+                 grid_spmm=None, stream=None):
+        """grid_fused / grid_spmm: the launch table, five workgroups-per-CU
+        entries for padded widths 4, 8, 16, 32, 64 (0 = built-in), as
+        tune_server returns it."""
         lib = N.load()
-        o = N.default_server_options()
-        o.max_active = int(max_active)
-        o.hbm_budget = float(hbm_budget)
-        o.ticks_per_poll = int(ticks_per_poll)
-        o.use_graph = int(bool(use_graph))
+        o = _server_options(max_active, hbm_budget, ticks_per_poll, use_graph, grid_fused,
+                            grid_spmm)
         h = ctypes.c_void_p()
         N.check(lib.fc_server_create(ctypes.byref(o), None if stream is None
                                      else int(stream.cuda_stream), ctypes.byref(h)))

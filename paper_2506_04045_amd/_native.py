@@ -31,7 +31,7 @@ EXPORTED = [
     "fc_gram", "fc_spectral_norm", "fc_last_error",
     "fc_server_opts_default", "fc_server_clock", "fc_server_create", "fc_server_submit",
     "fc_server_poll", "fc_server_get_u", "fc_server_release", "fc_server_stats",
-    "fc_server_destroy", "fc_hessian_vector", "fc_curvature",
+    "fc_server_destroy", "fc_server_tune", "fc_hessian_vector", "fc_curvature",
 ]
 
 
@@ -71,7 +71,8 @@ class KernelTimes(ctypes.Structure):
 class ServerOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_active", ctypes.c_int32),
                 ("hbm_budget", ctypes.c_double), ("ticks_per_poll", ctypes.c_int32),
-                ("use_graph", ctypes.c_int32)]
+                ("use_graph", ctypes.c_int32), ("grid_fused", ctypes.c_int32 * 5),
+                ("grid_spmm", ctypes.c_int32 * 5)]
 
 
 class Result(ctypes.Structure):
@@ -147,6 +148,11 @@ def load() -> ctypes.CDLL:
     lib.fc_server_get_u.restype = st
     lib.fc_server_release.argtypes = [P, ctypes.c_uint64]
     lib.fc_server_release.restype = st
+    lib.fc_server_tune.argtypes = [ctypes.POINTER(ServerOpts), i32, ctypes.POINTER(CSR),
+                                   ctypes.POINTER(Options), ctypes.POINTER(P), ctypes.c_int, P,
+                                   ctypes.POINTER(ServerOpts), ctypes.POINTER(f64),
+                                   ctypes.POINTER(i32)]
+    lib.fc_server_tune.restype = st
     lib.fc_server_stats.argtypes = [P, ctypes.POINTER(i32), ctypes.POINTER(i32),
                                     ctypes.POINTER(i64), ctypes.POINTER(f64)]
     lib.fc_server_stats.restype = st

@@ -49,6 +49,22 @@ def test_struct_layouts(N):
     assert o.eta == 2.0 and o.max_iter == 100 and o.check_every == 16
     assert o.precision == N.FC_PREC_FP32 and o.diag == N.FC_DIAG_UNIT and o.accelerate == 1
     assert o.tol_loss != o.tol_loss  # NaN disables the loss stop by default
+    so = N.default_server_options()
+    assert so.struct_size == ctypes.sizeof(N.ServerOpts) == 64
+    assert list(so.grid_fused) == [0] * 5 and list(so.grid_spmm) == [0] * 5
+
+
+def test_server_argument_errors_before_device_work(N):
+    lib = N.load()
+    so = N.default_server_options()
+    so.grid_spmm[3] = 65
+    h = ctypes.c_void_p()
+    assert lib.fc_server_create(ctypes.byref(so), None, ctypes.byref(h)) == N.FC_ERR_INVALID_ARG
+    assert b"launch table" in lib.fc_last_error()
+    best, rate = N.ServerOpts(), ctypes.c_double()
+    assert lib.fc_server_tune(ctypes.byref(N.default_server_options()), 0, None, None, None,
+                              N.FC_F32, None, ctypes.byref(best), ctypes.byref(rate),
+                              None) == N.FC_ERR_INVALID_ARG
 
 
 def test_argument_errors_before_device_work(N):

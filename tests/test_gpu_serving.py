@@ -159,3 +159,31 @@ def test_relabelled_requests_match_their_solo_runs(fc):
     for i in range(len(reqs)):
         r, U = served[i]
         assert r.status == 0 and r.f == alone[i][0].f and np.array_equal(U, alone[i][1])
+
+
+def test_tuned_schedule_keeps_every_result(fc):
+    """The autotuner runs the sample under many schedules (graph replay,
+    ticks per poll, launch-table entries per padded width), checks that none
+    changes a result, and returns a valid schedule; a server built from it
+    still gives every request its solo result."""
+    reqs = _requests(10, seed0=300, nmax=4000)
+    sample = [dict(row_ptr=wl.row_ptr, col_idx=wl.col_idx, val=wl.val, c=wl.c, U0=wl.U0, **SOLVE)
+              for wl in reqs]
+    t = fc.tune_server(sample, use_graph=False, ticks_per_poll=8)
+    print(f"tuned schedule {t}")
+    assert t["ticks_per_poll"] in (4, 8, 16, 32)
+    widths = {max(4, 1 << (wl.c - 1).bit_length()) for wl in reqs}
+    for k, cp in enumerate((4, 8, 16, 32, 64)):
+        if cp in widths:
+            assert t["grid_fused"][k] in (1, 2, 4) and t["grid_spmm"][k] in (4, 8, 16, 32)
+        else:
+            assert t["grid_fused"][k] == 0 and t["grid_spmm"][k] == 0
+    assert t["solves_per_s"] > 0 and t["runs"] >= 9
+    served = _serve(fc, reqs, dict(ticks_per_poll=t["ticks_per_poll"], use_graph=t["use_graph"],
+                                   grid_fused=t["grid_fused"], grid_spmm=t["grid_spmm"]))
+    for i, wl in enumerate(reqs):
+        r, U = served[i]
+        info, U_ref = _alone(fc, wl)
+        assert r.status == 0
+        assert r.f == info.f and r.iter == info.iter
+        assert np.array_equal(U, U_ref)
