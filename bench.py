@@ -274,6 +274,40 @@ def mixed_target_bench(args) -> dict:
     }
 
 
+def smaller_workloads_bench(args) -> dict:
+    """The two smaller workloads of the family: n = 2,000, c = 8 in FP64
+    (Dirichlet(0.3) planted rows, ER degree 20, sigma 0.02; 200 FISTA
+    iterations with tau = 1/L_thm from the power iteration; start 1/c), and
+    n = 1e6, c = 32 in FP32 (ER degree 30, overlapping communities, sigma
+    0.05; 500 FISTA iterations with backtracking, L0 = L_thm/100; start
+    Dirichlet(1) rows).  Iterations/s from one timed fc_step call after the
+    solver is set up, and the trials per iteration of the backtracking run."""
+    import torch
+    import paper_2506_04045_amd as fc
+    import workloads as W
+    out = {}
+    runs = (("fp64_n2000_c8", W.config_small_fp64(seed=0, device="cuda", u0="uniform"), 200,
+             dict(precision="fp64", step=0.0), None),
+            ("fp32_n1e6_c32_backtracking", W.config_medium(seed=0, device="cuda"), 500,
+             dict(precision="fp32", backtrack=True), "U0"))
+    for name, wl, iters, kw, u0 in runs:
+        torch.cuda.synchronize()
+        with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0 if u0 else None, **kw) as s:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = s.step(iters)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        out[name] = {"n": wl.n, "c": wl.c, "nnz": wl.nnz, "iterations": info.iter,
+                     "seconds": dt, "iters_per_s": info.iter / dt,
+                     "trials_per_iteration": info.trials / max(1, info.iter), "f": info.f}
+        log(f"{name}: {info.iter} iterations in {dt:.3f} s ({info.iter / dt:.0f} it/s, "
+            f"{info.trials / max(1, info.iter):.2f} trials per iteration)")
+        del wl
+    torch.cuda.empty_cache()
+    return out
+
+
 def artificial_bench(args) -> dict:
     """The paper's artificial two-cluster graph (section 5): 500,000 + 250,000
     nodes of expected degree 1,200 and 1,600, 200 bridges, C = 2, S = A + I,
@@ -326,6 +360,8 @@ def main() -> int:
                     help="Beck-Teboulle backtracking (L0 = L_thm/100) instead of the constant step")
     ap.add_argument("--defer-loss", type=int, default=1,
                     help="1: each iterate's loss is formed during the next pass (fc_options.defer_loss)")
+    ap.add_argument("--no-smaller", action="store_true",
+                    help="skip the n = 2,000 FP64 and n = 1e6 backtracking runs")
     ap.add_argument("--no-artificial", action="store_true",
                     help="skip the artificial two-cluster graph run")
     ap.add_argument("--target-iters", type=int, default=100,
@@ -450,6 +486,9 @@ def main() -> int:
     artificial = None
     if not args.no_artificial:
         artificial = artificial_bench(args)
+    smaller = None
+    if not args.no_smaller:
+        smaller = smaller_workloads_bench(args)
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, c, n, nnz)
@@ -487,6 +526,7 @@ def main() -> int:
         "serving": serving,
         "mixed_time_to_target": mixed_target,
         "artificial_two_cluster": artificial,
+        "smaller_workloads": smaller,
     }
     print(json.dumps(out), flush=True)
     return 0
