@@ -1044,7 +1044,10 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
     // LDS row stride: float rows are offset by half the banks between the four
     // row groups an MFMA operand read touches; double rows only need padding
     constexpr int STRIDE = sizeof(T) == 8 ? CPM + 4 : CPM + (CPM == 16 ? 32 : 16);
-    constexpr int NMAT = 1 + (ACCEL ? 1 : 0) + (BT ? 2 : 0);
+    // staged tiles: p, the next extrapolated point (ACCEL), y (BT; the
+    // line-search operands p + y and p - y are formed from p and y as they
+    // are read, which costs a tile of LDS less than staging both)
+    constexpr int NMAT = 1 + (ACCEL ? 1 : 0) + (BT ? 1 : 0);
     constexpr int NSYM = SymBlocks<M>::N;
     constexpr int NBLK = NSYM + (ACCEL ? NSYM : 0) + (BT ? M * M : 0);
     constexpr int BPW = (NBLK + 3) / 4;  // Gram blocks per wave
@@ -1237,10 +1240,8 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
             lds[0][lrow * STRIDE + k] = p[s];
             if constexpr (ACCEL)
                 lds[1][lrow * STRIDE + k] = bn1 * p[s] - bn0 * xc[s];
-            if constexpr (BT) {
-                lds[NMAT - 2][lrow * STRIDE + k] = p[s] + y[s];
-                lds[NMAT - 1][lrow * STRIDE + k] = p[s] - y[s];
-            }
+            if constexpr (BT)
+                lds[NMAT - 1][lrow * STRIDE + k] = y[s];
         }
         __syncthreads();
         // the new iterate (and its bfloat16 copy for the next sparse product): a
@@ -1286,25 +1287,32 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
         for (int kk = 0; kk < BPW; ++kk) {
             const int kb = wave + 4 * kk;
             if (kb < NBLK) {
-                int m1, m2, a, b;
+                int m, a, b;
+                bool cross = false;   // (p + y)^T (p - y)
                 if (kb < NSYM) {
-                    m1 = m2 = 0;
+                    m = 0;
                     SymBlocks<M>::ab(kb, a, b);
                 } else if (ACCEL && kb < 2 * NSYM) {
-                    m1 = m2 = 1;
+                    m = 1;
                     SymBlocks<M>::ab(kb - NSYM, a, b);
                 } else {
                     const int q = kb - NSYM - (ACCEL ? NSYM : 0);
-                    m1 = NMAT - 2;
-                    m2 = NMAT - 1;
+                    m = 0;
+                    cross = true;
                     a = q / M;
                     b = q % M;
                 }
                 A4 acc = A4{0, 0, 0, 0};
 #pragma unroll
-                for (int t = 0; t < 16; ++t)
-                    acc = mfma16x16x4(lds[m1][(4 * t + g) * STRIDE + 16 * a + r],
-                                      lds[m2][(4 * t + g) * STRIDE + 16 * b + r], acc);
+                for (int t = 0; t < 16; ++t) {
+                    const int ia = (4 * t + g) * STRIDE + 16 * a + r, ib = (4 * t + g) * STRIDE + 16 * b + r;
+                    T va = lds[m][ia], vb = lds[m][ib];
+                    if (BT && cross) {
+                        va = va + lds[NMAT - 1][ia];
+                        vb = vb - lds[NMAT - 1][ib];
+                    }
+                    acc = mfma16x16x4(va, vb, acc);
+                }
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
                     acc64[kk][q] += (double)acc[q];
@@ -1351,7 +1359,7 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
 // ask for four waves per SIMD (measured 6 % faster at c = 32 than the three
 // the compiler picks alone).
 template <typename T, int CP, bool BT> constexpr int fused_min_waves() {
-    return sizeof(T) == 4 && !BT && CP <= 32 ? 4 : 1;
+    return sizeof(T) == 4 && CP <= 32 ? (BT ? 3 : 4) : 1;
 }
 
 template <typename T, int CP, bool ACCEL, bool BT, bool SHADOW>
