@@ -552,9 +552,9 @@ template <> struct AccumOf<__hip_bfloat16> { typedef float type; };
 // indices and values of the next pass are loaded while the gathers of the
 // current one are in flight, which takes one dependent load off every pass
 // (measured 28.2 -> 27.4 ms at n = 7e7, c = 32, at seven instead of eight
-// waves per SIMD; the bfloat16 and FP64 products lose more occupancy than
-// they gain and keep the plain loop).  Both loops add the same terms in the
-// same order.
+// waves per SIMD; the bfloat16 product measured slower that way, dropping
+// from six waves to five, and it and the FP64 product keep the plain loop).
+// Both loops add the same terms in the same order.
 template <typename TU, typename VS, int CP, int SLOTS, int DEPTH, typename TA, int NE>
 __device__ __forceinline__ void team_row_sum(const int32_t *__restrict__ col,
                                              const VS *__restrict__ val,
@@ -1357,7 +1357,8 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
 
 // FP32 up to 32 clusters without the line-search sums fits 128 registers:
 // ask for four waves per SIMD (measured 6 % faster at c = 32 than the three
-// the compiler picks alone).
+// the compiler picks alone); with them it fits 168, three waves (10.6 vs
+// 11.1 ms at n = 7e7 against two).
 template <typename T, int CP, bool BT> constexpr int fused_min_waves() {
     return sizeof(T) == 4 && CP <= 32 ? (BT ? 3 : 4) : 1;
 }
