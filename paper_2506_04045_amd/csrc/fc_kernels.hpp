@@ -1358,9 +1358,12 @@ __device__ __forceinline__ void fused_body(const Inst &I, int64_t blk, int64_t n
 // FP32 up to 32 clusters without the line-search sums fits 128 registers:
 // ask for four waves per SIMD (measured 6 % faster at c = 32 than the three
 // the compiler picks alone); with them it fits 168, three waves (10.6 vs
-// 11.1 ms at n = 7e7 against two).
+// 11.1 ms at n = 7e7 against two).  At 64 clusters two waves instead of the
+// one the compiler picks alone: 12.5 vs 18.9 ms for the same bytes
+// (n = 3.5e7), 11.7 vs 15.6 ms with the line-search sums (a few spilled
+// registers).
 template <typename T, int CP, bool BT> constexpr int fused_min_waves() {
-    return sizeof(T) == 4 && CP <= 32 ? (BT ? 3 : 4) : 1;
+    return sizeof(T) == 4 ? (CP <= 32 ? (BT ? 3 : 4) : 2) : 1;
 }
 
 template <typename T, int CP, bool ACCEL, bool BT, bool SHADOW>
@@ -1368,8 +1371,10 @@ __global__ __launch_bounds__(256, (fused_min_waves<T, CP, BT>())) void k_fused_1
     if (inst_active(I))
         fused_body<T, CP, ACCEL, BT, SHADOW>(I, blockIdx.x, gridDim.x);
 }
+// The batched form holds more state per lane; FP32 asks for two waves per
+// SIMD (at 64 clusters the compiler alone picks one).
 template <typename T, int CP, bool ACCEL, bool BT, bool SHADOW>
-__global__ __launch_bounds__(256) void k_fused_b(const Inst *__restrict__ insts,
+__global__ __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) void k_fused_b(const Inst *__restrict__ insts,
                                                  const VBlk *__restrict__ tab,
                                                  const int32_t *__restrict__ count) {
     for (int64_t vb = blockIdx.x; vb < *count; vb += gridDim.x) {
