@@ -1456,7 +1456,8 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
     if (!I.defer) {
         const int64_t np = (int64_t)I.g_spmm + I.g_comb;
         double a = 0.0;
-        for (int64_t q = tid; q < np; q += 256)
+#pragma unroll 8
+        for (int64_t q = tid; q < np; q += 256)   // loads run ahead, adds stay in order
             a += I.part_spmm[q];
         sh[tid] = a;
         __syncthreads();

@@ -919,10 +919,10 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
                 rows_per_wg = SpmmCfg<__hip_bfloat16, CP>::ROWS_PER_WG;
             return FC_OK;
         });
-        // persistent workgroups per CU; a deferred instance's product has no
-        // partials to reduce, so it takes a wider grid (measured 28.3 vs
-        // 29.0 ms at n = 7e7, c = 32, with 1024 instead of 64 per CU)
-        h->g_spmm = grid_1d(h->n, rows_per_wg, (int64_t)cus * (h->defer ? 1024 : 64));
+        // persistent workgroups per CU (measured 28.3 vs 29.0 ms at n = 7e7,
+        // c = 32, with 1024 instead of 64 per CU; the controller sums the
+        // workgroups' loss partials, when there are any, in about 0.1 ms)
+        h->g_spmm = grid_1d(h->n, rows_per_wg, (int64_t)cus * 1024);
     }
     st = build_heavy_plan(h->row_ptr, S->n, h->prec == FC_PREC_FP64 ? 8 : 4, h->cp, s, h->heavy);
     if (st != FC_OK)
