@@ -1400,18 +1400,49 @@ __global__ __launch_bounds__(256) void k_trace_fused(Inst I) {
     const T *__restrict__ Xc = (const T *)I.X[I.st->role[ROLE_C]];
     const T *__restrict__ Zc = (const T *)I.Z[I.st->role[ROLE_C]];
     const int64_t n = I.n, nwt = nwt_of(n);
-    double sc_trc = 0.0;
-    for (int64_t wt = blockIdx.x; wt < nwt; wt += gridDim.x) {
+    // a lane's slots of one tile (zero past the end); FP32 slots 4a..4a+3 are
+    // four consecutive components, loaded as one 16-byte piece
+    auto load = [&](int64_t wt, T (&xc)[NC], T (&zc)[NC]) {
         const int64_t row = wt * 64 + wave * 16 + r;
-        T xc[NC], zc[NC];
+        const bool live = wt < nwt && row < n;
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            if constexpr (sizeof(T) == 4) {
+                const int k0 = 16 * a + 4 * g;
+                T tx[4] = {0, 0, 0, 0}, tz[4] = {0, 0, 0, 0};
+                if (live && k0 < CP) {
+                    GatherLoad<T, 4>::load(Xc + row * CP + k0, tx);
+                    GatherLoad<T, 4>::load(Zc + row * CP + k0, tz);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    xc[4 * a + q] = tx[q];
+                    zc[4 * a + q] = tz[q];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int k = kslot<T>(4 * a + q, g);
+                    const bool ok = live && k < CP;
+                    xc[4 * a + q] = ok ? Xc[row * CP + k] : (T)0;
+                    zc[4 * a + q] = ok ? Zc[row * CP + k] : (T)0;
+                }
+            }
+        }
+    };
+    // the next tile's loads are in flight while the current one is summed;
+    // the terms are added in tile order, as the fused kernel adds them
+    double sc_trc = 0.0;
+    T xc[NC], zc[NC], xn[NC], zn[NC];
+    load(blockIdx.x, xc, zc);
+    for (int64_t wt = blockIdx.x; wt < nwt; wt += gridDim.x) {
+        load(wt + gridDim.x, xn, zn);
+        sc_trc += trace_terms<T, NC>(xc, zc, I.diag_unit);
 #pragma unroll
         for (int s = 0; s < NC; ++s) {
-            const int k = kslot<T>(s, g);
-            const bool ok = row < n && k < CP;
-            xc[s] = ok ? Xc[row * CP + k] : (T)0;
-            zc[s] = ok ? Zc[row * CP + k] : (T)0;
+            xc[s] = xn[s];
+            zc[s] = zn[s];
         }
-        sc_trc += trace_terms<T, NC>(xc, zc, I.diag_unit);
     }
     double vals[6] = {0.0, 0.0, 0.0, 0.0, 0.0, sc_trc};
     fused_scalars_out(vals, I.part_fused + (int64_t)blockIdx.x * L::NE + 3 * L::MAT);
