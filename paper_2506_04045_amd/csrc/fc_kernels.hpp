@@ -989,9 +989,11 @@ __device__ __forceinline__ double simplex_threshold(const T (&v)[NC], const bool
 // v = y - tau grad, p = P_simplex(v), y' = (1+beta') p - beta' xc.
 // The constant mu removed from G_Y changes every gradient row by a
 // multiple of the ones vector, which the projection ignores; it is added
-// back in the line-search sum.  The workgroup then stages p, y' (and
-// p + y, p - y when backtracking) in LDS and each wave accumulates some of
-// the 16 x 16 blocks of their Gram matrices on the matrix cores.
+// back in the line-search sum.  The workgroup then stages p, y' (and y when
+// backtracking) in LDS, writes p from there in contiguous pieces, and each
+// wave accumulates some of the 16 x 16 blocks of the Gram matrices of p and
+// y' (and of the line-search cross sum (p + y)^T (p - y)) on the matrix
+// cores.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t nwt_of(int64_t n) { return (n + 63) / 64; }
 
