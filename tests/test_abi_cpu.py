@@ -128,3 +128,15 @@ def test_binding_fails_loudly_without_the_library(tmp_path, monkeypatch):
     monkeypatch.setattr(_native, "_lib", None)
     with pytest.raises(RuntimeError, match="no CPU fallback"):
         _native.load()
+
+
+def test_tuner_and_launch_table_arguments_in_the_binding(N):
+    import paper_2506_04045_amd as fc
+    with pytest.raises(ValueError):
+        fc.tune_server([])
+    with pytest.raises(ValueError):
+        fc._server_options(64, 2.0**30, 8, False, grid_fused=[1, 2, 3])
+    o = fc._server_options(64, 2.0**30, 16, False, grid_fused=[1, 2, 4, 2, 1],
+                           grid_spmm=[4, 8, 16, 32, 8])
+    assert list(o.grid_fused) == [1, 2, 4, 2, 1] and list(o.grid_spmm) == [4, 8, 16, 32, 8]
+    assert o.ticks_per_poll == 16 and o.use_graph == 0
