@@ -161,6 +161,7 @@ struct Inst {
     int32_t g_fused, g_spmm, g_comb, g_red;
     int32_t defer;   // 1: products hold S_off X (no unit diagonal, no trace terms)
     int32_t pad0;
+    int64_t nt_from; // FP32 products gather rows >= nt_from non-temporally (0: none)
     const double *sched;
     double *hist_f, *hist_tau, *hist_r;
     int32_t *hist_trials;
@@ -542,6 +543,24 @@ template <int NE> struct GatherLoad<__hip_bfloat16, NE> {
     }
 };
 
+// FP32 rows gathered with the non-temporal hint: rows that are rarely
+// gathered again then stay out of the way of the ones that are (the hint
+// also keeps them out of the memory-side Infinity Cache).
+template <int NE> struct GatherLoadNT {
+    __device__ __forceinline__ static void load(const float *p, float (&out)[NE]) {
+        static_assert(NE % 4 == 0, "float rows load in float4 pieces");
+        typedef float f4v __attribute__((ext_vector_type(4)));
+#pragma unroll
+        for (int q = 0; q < NE / 4; ++q) {
+            const f4v t = __builtin_nontemporal_load(reinterpret_cast<const f4v *>(p) + q);
+            out[4 * q + 0] = t.x;
+            out[4 * q + 1] = t.y;
+            out[4 * q + 2] = t.z;
+            out[4 * q + 3] = t.w;
+        }
+    }
+};
+
 template <typename T> struct AccumOf { typedef T type; };
 template <> struct AccumOf<__hip_bfloat16> { typedef float type; };
 
@@ -554,12 +573,13 @@ template <> struct AccumOf<__hip_bfloat16> { typedef float type; };
 // (measured 28.2 -> 27.4 ms at n = 7e7, c = 32, at seven instead of eight
 // waves per SIMD; the bfloat16 product measured slower that way, dropping
 // from six waves to five, and it and the FP64 product keep the plain loop).
-// Both loops add the same terms in the same order.
+// Both loops add the same terms in the same order.  FP32 rows at index
+// nt_from and beyond (when nt_from > 0) are gathered non-temporally.
 template <typename TU, typename VS, int CP, int SLOTS, int DEPTH, typename TA, int NE>
 __device__ __forceinline__ void team_row_sum(const int32_t *__restrict__ col,
                                              const VS *__restrict__ val,
                                              const TU *__restrict__ U, int64_t beg, int64_t end,
-                                             int slot, int sub, TA (&acc)[NE]) {
+                                             int slot, int sub, TA (&acc)[NE], int64_t nt_from) {
     if constexpr (std::is_same<TU, float>::value) {
         int32_t jn[DEPTH];   // column of the next pass's nonzero u, -1 past the row's end
         TA sn[DEPTH];
@@ -578,8 +598,12 @@ __device__ __forceinline__ void team_row_sum(const int32_t *__restrict__ col,
 #pragma unroll
                 for (int q = 0; q < NE; ++q)
                     g[u][q] = (TA)0;
-                if (jn[u] >= 0)
-                    GatherLoad<TU, NE>::load(U + (int64_t)jn[u] * CP + sub * NE, g[u]);
+                if (jn[u] >= 0) {
+                    if (nt_from > 0 && jn[u] >= nt_from)
+                        GatherLoadNT<NE>::load(U + (int64_t)jn[u] * CP + sub * NE, g[u]);
+                    else
+                        GatherLoad<TU, NE>::load(U + (int64_t)jn[u] * CP + sub * NE, g[u]);
+                }
             }
 #pragma unroll
             for (int u = 0; u < DEPTH; ++u) {
@@ -716,7 +740,8 @@ __device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, 
                 if (end - beg > light_max)
                     live = false;
                 else
-                    team_row_sum<TU, VS, CP, Lc::SLOTS, DEPTH>(col, val, U, beg, end, slot, sub, acc);
+                    team_row_sum<TU, VS, CP, Lc::SLOTS, DEPTH>(col, val, U, beg, end, slot, sub, acc,
+                                                               I.nt_from);
             }
             team_slot_sum<Lc::GS, Lc::TEAM>(acc);
             trace_acc += row_epilogue<Lc::GS, TA, TZ, TX, CP>(live, slot, sub, row, X, Z, diag_unit,
@@ -734,7 +759,7 @@ __device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, 
             for (int q = 0; q < NE; ++q)
                 acc[q] = (TA)0;
             team_row_sum<TU, VS, CP, Wc::SLOTS, DEPTH>(col, val, U, row_ptr[row], row_ptr[row + 1],
-                                                        slot, sub, acc);
+                                                        slot, sub, acc, I.nt_from);
             team_slot_sum<Wc::GS, Wc::TEAM>(acc);
             trace_acc += row_epilogue<Wc::GS, TA, TZ, TX, CP>(true, slot, sub, row, X, Z, diag_unit,
                                                               plain, acc);
@@ -749,7 +774,7 @@ __device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, 
                 acc[q] = (TA)0;
             const int64_t beg = chunk_beg[k];
             team_row_sum<TU, VS, CP, Wc::SLOTS, DEPTH>(col, val, U, beg, beg + chunk_len[k], slot, sub,
-                                                        acc);
+                                                        acc, I.nt_from);
             team_slot_sum<Wc::GS, Wc::TEAM>(acc);
             if (slot == 0)
 #pragma unroll
