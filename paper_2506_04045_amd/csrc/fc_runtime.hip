@@ -969,13 +969,16 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
         I.hist_trials = h->d_hist_trials;
         I.sched = nullptr;
         I.defer = h->defer;
-        // relabelled FP32 instances: the rows past the first 256 MB of X (the
-        // size of MI355X's Infinity Cache; the most-gathered rows come first)
-        // are gathered non-temporally, which keeps the cache for the hot rows
-        // (27.3 -> 26.7 ms at n = 7e7, c = 32; 1, 4 and 8 times the size:
-        // 26.8, 26.9, 27.2 ms)
+        // relabelled FP32 instances whose rows fill whole 128-byte lines: the
+        // rows past the first 256 MB of X (the size of MI355X's Infinity
+        // Cache; the most-gathered rows come first) are gathered
+        // non-temporally, which keeps the cache for the hot rows (27.3 ->
+        // 26.7 ms at n = 7e7, c = 32; 1, 4 and 8 times the size: 26.8, 26.9,
+        // 27.2 ms).  Rows that share a line (64-byte bfloat16 rows) measured
+        // slower with the hint.
         const int64_t cache_rows = (int64_t)(256ll << 20) / ((int64_t)h->cp * 4);
-        I.nt_from = h->reorder == FC_REORDER_DEGREE && h->prec == FC_PREC_FP32 && cache_rows < h->n
+        I.nt_from = h->reorder == FC_REORDER_DEGREE && h->prec == FC_PREC_FP32 && h->cp >= 32 &&
+                            cache_rows < h->n
                         ? cache_rows
                         : 0;
     }
