@@ -213,7 +213,9 @@ def mixed_target_bench(args) -> dict:
     values, bfloat16 gathered rows) starts from the same U0 with the same tau
     and runs until its iterate's objective, evaluated on the FP32 values,
     reaches f_FP32(K) + 1e-6 (f(U0) - f_FP32(K)).  Objective checks are not
-    timed."""
+    timed.  Both runs are deterministic; each is made twice, interleaved, and
+    the shorter time of each counts (a run timed from a fresh solver varies
+    by several percent)."""
     import torch
     import paper_2506_04045_amd as fc
     import workloads as W
@@ -223,43 +225,55 @@ def mixed_target_bench(args) -> dict:
     torch.cuda.synchronize()
     torch.cuda.empty_cache()   # hand the generator's scratch back before the solvers allocate
     log(f"mixed target: nnz={wl.nnz:,}")
-    # tau = 1/L_thm with ||S||_F for ||S||_2, as the paper's experiments do
-    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 32, wl.U0, precision="fp32", step=0.0,
-                   norm_estimate="frobenius", reorder=args.reorder,
-                   defer_loss=bool(args.defer_loss)) as s:
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        info = s.step(K)
-        torch.cuda.synchronize()
-        t_fp32 = time.perf_counter() - t0
-        hist = s.history()
-        f0, f_k, tau = float(hist["f"][0]), float(info.f), float(hist["tau"][1])
-        U = s.get_u()
-        f_k_check = fc.objective(wl.row_ptr, wl.col_idx, wl.val, U)
-        del U
-    df = f0 - f_k
-    target = f_k_check + 1e-6 * df
-    log(f"mixed target: FP32 {K} iterations in {t_fp32:.2f} s, f={f_k_check:.9e}, target {target:.9e}")
-    elapsed, it, f_mixed = 0.0, 0, math.inf
-    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 32, wl.U0, precision="mixed", step=tau,
-                   reorder=args.reorder, defer_loss=bool(args.defer_loss)) as s:
-        chunk = max(1, K - 5)
-        while it < 2 * K:
+    def fp32_run():
+        # tau = 1/L_thm with ||S||_F for ||S||_2, as the paper's experiments do
+        with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 32, wl.U0, precision="fp32", step=0.0,
+                       norm_estimate="frobenius", reorder=args.reorder,
+                       defer_loss=bool(args.defer_loss)) as s:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            s.step(chunk)
+            info = s.step(K)
             torch.cuda.synchronize()
-            elapsed += time.perf_counter() - t0
-            it += chunk
+            t = time.perf_counter() - t0
+            hist = s.history()
             U = s.get_u()
-            f_mixed = fc.objective(wl.row_ptr, wl.col_idx, wl.val, U)
+            f_check = fc.objective(wl.row_ptr, wl.col_idx, wl.val, U)
             del U
-            if f_mixed <= target:
-                break
-            chunk = 1
+            return t, float(hist["f"][0]), float(info.f), float(hist["tau"][1]), f_check
+
+    def mixed_run(tau, target):
+        elapsed, it, f_mixed = 0.0, 0, math.inf
+        with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 32, wl.U0, precision="mixed", step=tau,
+                       reorder=args.reorder, defer_loss=bool(args.defer_loss)) as s:
+            chunk = max(1, K - 5)
+            while it < 2 * K:
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s.step(chunk)
+                torch.cuda.synchronize()
+                elapsed += time.perf_counter() - t0
+                it += chunk
+                U = s.get_u()
+                f_mixed = fc.objective(wl.row_ptr, wl.col_idx, wl.val, U)
+                del U
+                if f_mixed <= target:
+                    break
+                chunk = 1
+        return elapsed, it, f_mixed
+
+    t_fp32s, t_mixeds = [], []
+    for rep in range(2):
+        t, f0, f_k, tau, f_k_check = fp32_run()
+        t_fp32s.append(t)
+        df = f0 - f_k
+        target = f_k_check + 1e-6 * df
+        log(f"mixed target: FP32 {K} iterations in {t:.2f} s, f={f_k_check:.9e}, target {target:.9e}")
+        elapsed, it, f_mixed = mixed_run(tau, target)
+        t_mixeds.append(elapsed)
+        log(f"mixed target: mixed {'reached' if f_mixed <= target else 'did not reach'} it after "
+            f"{it} iterations in {elapsed:.2f} s (f={f_mixed:.9e})")
+    t_fp32, elapsed = min(t_fp32s), min(t_mixeds)
     reached = f_mixed <= target
-    log(f"mixed target: mixed {'reached' if reached else 'did not reach'} it after {it} "
-        f"iterations in {elapsed:.2f} s (f={f_mixed:.9e})")
     del wl
     torch.cuda.empty_cache()
     return {
@@ -267,9 +281,10 @@ def mixed_target_bench(args) -> dict:
                      f"unit diagonal, FISTA tau=1/L_thm with ||S||_F, articles relabelled: "
                      f"{args.reorder}"),
         "target": "f <= f_FP32(K) + 1e-6 (f(U0) - f_FP32(K)), objective on the FP32 values",
-        "K": K, "fp32": {"iters": K, "seconds": t_fp32, "iters_per_s": K / t_fp32, "f": f_k_check},
+        "K": K, "fp32": {"iters": K, "seconds": t_fp32, "iters_per_s": K / t_fp32, "f": f_k_check,
+                         "seconds_each_run": t_fp32s},
         "mixed": {"iters": it, "seconds": elapsed, "iters_per_s": it / elapsed, "f": f_mixed,
-                  "reached": reached},
+                  "reached": reached, "seconds_each_run": t_mixeds},
         "speedup_time_to_target": (t_fp32 / elapsed) if reached else None,
     }
 
