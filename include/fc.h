@@ -304,8 +304,10 @@ typedef struct {
                                (default 32 GiB); a request larger than the whole
                                budget finishes with FC_ERR_OUT_OF_MEMORY */
     int32_t ticks_per_poll; /* trials launched between reads of the request states
-                               (default 8) */
-    int32_t use_graph;      /* 1: replay each tick from a captured hipGraph (default) */
+                               (default 16) */
+    int32_t use_graph;      /* 1: replay each tick from a captured hipGraph on the
+                               server's stream; 0 (default): direct launches, one
+                               stream per group of requests */
     /* Launch table of the batched kernels, indexed by padded width (0..4 for
        4, 8, 16, 32, 64 columns): persistent workgroups per compute unit that
        walk the (instance, block) tables of the fused kernel (grid_fused) and

@@ -254,7 +254,7 @@ def _server_options(max_active, hbm_budget, ticks_per_poll, use_graph, grid_fuse
 
 
 def tune_server(requests, max_active: int = 64, hbm_budget: float = 32.0 * 2**30,
-                ticks_per_poll: int = 8, use_graph: bool = True, stream=None) -> dict:
+                ticks_per_poll: int = 16, use_graph: bool = False, stream=None) -> dict:
     """fc_server_tune on sample requests, each a dict with row_ptr, col_idx,
     val, c, U0 (or None) and solver options as Solver takes them.  Returns
     the chosen schedule (ticks_per_poll, use_graph, grid_fused, grid_spmm:
@@ -302,7 +302,7 @@ class Server:
     borrowed until the request is released."""
 
     def __init__(self, max_active: int = 64, hbm_budget: float = 32.0 * 2**30,
-                 ticks_per_poll: int = 8, use_graph: bool = True, grid_fused=None,
+                 ticks_per_poll: int = 16, use_graph: bool = False, grid_fused=None,
                  grid_spmm=None, stream=None):
         """grid_fused / grid_spmm: the launch table, five workgroups-per-CU
         entries for padded widths 4, 8, 16, 32, 64 (0 = built-in), as
