@@ -4,11 +4,12 @@ This package is the slow, independent reference the HIP path is checked
 against.  Only the tests, the smoke check and the CPU-baseline leg of the
 benchmark may import it; the library itself never does, and the two share no
 code.  Every function here is a thin ctypes wrapper over ``fcref.c`` (plain C,
-IEEE double), which follows the paper's algorithms step by step:
+IEEE double), which computes what the paper's formulas and algorithms define:
 
 * ``x_s``               -- the products X s_i of eq. (gradient_column), section 3
 * ``share``             -- share = X X^T, Alg. 2
-* ``project_simplex``   -- the Duchi projection, Alg. 1
+* ``project_simplex``   -- the Euclidean projection onto the simplex (section 2),
+                           from its optimality conditions (the result Alg. 1 computes)
 * ``loss``              -- the structured loss of Alg. 3
 * ``gradient``          -- eq. (gradient_column), column by column
 * ``spectral_norm``     -- power iteration for ||S||_2 (Theorem 3.1's bound)
@@ -175,7 +176,9 @@ def step_rows(rows, sub_row_ptr, sub_col_idx, sub_val, diag_unit: bool, X, tau: 
 
 
 def project_simplex(x) -> np.ndarray:
-    """Duchi projection of one vector onto the unit simplex, Alg. 1."""
+    """Euclidean projection of one vector onto the unit simplex (section 2;
+    the threshold of its optimality conditions found by bisection, then
+    formed exactly from the support)."""
     x = np.ascontiguousarray(x, dtype=np.float64).reshape(-1)
     y = np.empty_like(x)
     _load().fcref_project_simplex(x.shape[0], _ptr(x), _ptr(y))
@@ -183,7 +186,7 @@ def project_simplex(x) -> np.ndarray:
 
 
 def project_columns(V) -> np.ndarray:
-    """P_Omega: the Duchi projection applied to every row of an (N, C) array."""
+    """P_Omega: the simplex projection applied to every row of an (N, C) array."""
     V = np.ascontiguousarray(V, dtype=np.float64)
     out = np.empty_like(V)
     _load().fcref_project_columns(V.shape[0], V.shape[1], _ptr(V), _ptr(out))

@@ -142,35 +142,55 @@ void fcref_x_s_rows(int64_t m, const int64_t *rows, const int64_t *sub_row_ptr,
     }
 }
 
-static int cmp_desc(const void *a, const void *b)
+/* Euclidean projection of one C-vector onto the unit simplex (the projection
+ * problem of section 2), written from its optimality conditions rather than
+ * from the sorting procedure of Alg. 1.  The minimiser is y_k = max(x_k - theta, 0)
+ * for the one theta at which h(theta) = sum_k max(x_k - theta, 0) equals 1.
+ * h is continuous and non-increasing, h(max_k x_k - 1) >= 1 (the largest term
+ * alone is 1) and h(max_k x_k) = 0, so theta lies in that bracket and bisection
+ * narrows it until the two ends are adjacent doubles (or 200 halvings).  The
+ * bracket then fixes the support A = {k : x_k > lo}, and theta is formed from
+ * the support alone as (sum_{k in A} x_k - 1) / |A|, the condition h = 1
+ * restricted to A.  A component that lies inside the final bracket changes
+ * that value by no more than the bracket's width, so including it is harmless.
+ * x and y may alias. */
+static double simplex_excess(int C, const double *x, double theta)
 {
-    const double x = *(const double *)a, y = *(const double *)b;
-    return (x < y) - (x > y);
+    double h = 0.0;
+    for (int k = 0; k < C; ++k)
+        if (x[k] > theta)
+            h += x[k] - theta;
+    return h - 1.0;
 }
 
-/* Euclidean projection of one C-vector onto the unit simplex by the Duchi
- * algorithm (Alg. 1): sort descending, prefix sums S_k, the largest k with
- * x_(k) - (S_k - 1)/k >= 0, threshold tau = (S_k - 1)/k, y = max(x - tau, 0).
- * x and y may alias. */
 void fcref_project_simplex(int C, const double *x, double *y)
 {
-    double stackbuf[128];
-    double *sorted = C <= 128 ? stackbuf : (double *)malloc(sizeof(double) * C);
-    memcpy(sorted, x, sizeof(double) * C);
-    qsort(sorted, C, sizeof(double), cmp_desc);
-    double prefix = 0.0, tau = 0.0;
-    for (int k = 1; k <= C; ++k) {
-        prefix += sorted[k - 1];
-        const double cand = (prefix - 1.0) / (double)k;
-        if (sorted[k - 1] - cand >= 0.0)
-            tau = cand; /* keeps the threshold of the largest such k */
+    double top = x[0];
+    for (int k = 1; k < C; ++k)
+        if (x[k] > top)
+            top = x[k];
+    double lo = top - 1.0, hi = top;  /* h(lo) >= 0 > h(hi) */
+    for (int pass = 0; pass < 200; ++pass) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(mid > lo && mid < hi))
+            break;
+        if (simplex_excess(C, x, mid) >= 0.0)
+            lo = mid;
+        else
+            hi = mid;
     }
+    double sum = 0.0;
+    int count = 0;
+    for (int k = 0; k < C; ++k)
+        if (x[k] > lo) {
+            sum += x[k];
+            ++count;
+        }
+    const double theta = (sum - 1.0) / (double)count;
     for (int k = 0; k < C; ++k) {
-        const double v = x[k] - tau;
+        const double v = x[k] - theta;
         y[k] = v > 0.0 ? v : 0.0;
     }
-    if (sorted != stackbuf)
-        free(sorted);
 }
 
 /* P_Omega applied column by column (section 2, "Projection onto Omega"). */
@@ -342,18 +362,21 @@ typedef struct {
 enum { FCREF_STOP_MAXITER = 0, FCREF_STOP_LOSS = 1, FCREF_STOP_PGRAD = 2,
        FCREF_STOP_STEP = 3 };
 
-/* Full solver following Alg. 4 (accelerate = 1) or Alg. 2/3 (accelerate = 0,
- * where the inertial term is dropped and Y_n = Xbar_{n-1}).
+/* The solver of Alg. 4 (accelerate = 1) and of Alg. 2/3 (accelerate = 0, no
+ * inertial term, so every step starts from the previous output).
  *
- * Initialisation (Alg. 4): Xbar_0 = X0, Y_1 = Xbar_0, t_1 = 1,
- * loss_0 = f(Xbar_0).  Iteration n = 1..max_iter:
- *   share = Y_n Y_n^T, grad_i = -4 (Y_n s_i - share y_i),
- *   xbar_i = P_simplex(y_i - tau_n grad_i)                       (basic GPA)
- *   loss_n = f(Xbar_n) by the structured formula of Alg. 3      (check loss)
- *   stop if loss_{n-1} - loss_n <= tol (the decrease reading of the stop
- *   test; output Xbar_n)
- *   t_{n+1} = (1 + sqrt(1 + 4 t_n^2)) / 2,
- *   Y_{n+1} = Xbar_n + ((t_n - 1)/t_{n+1}) (Xbar_n - Xbar_{n-1}).
+ * State: the latest output Xbar, the output before it, the point Y at which
+ * the next gradient is taken, and the scalar t of the inertial sequence.  All
+ * three points start at X0, t starts at 1, and the loss of X0 is recorded.
+ * Each iteration n takes a projected gradient step from Y_n: the gradient is
+ * formed column by column from share = Y_n Y_n^T and the products Y_n s_i
+ * (eq. gradient_column), every column of Y_n - tau_n grad is projected onto
+ * the simplex, and the result becomes Xbar_n, whose loss is formed from its
+ * own share and products (the structured loss of Alg. 3).  The run ends after
+ * max_iter iterations, or earlier when the loss fell by no more than tol_loss
+ * (read as a decrease test; Xbar_n is the output).  Otherwise t is advanced by
+ * t <- (1 + sqrt(1 + 4 t^2)) / 2 and Y_{n+1} moves from Xbar_n along
+ * Xbar_n - Xbar_{n-1} by the weight (t_old - 1) / t_new (zero for GPA).
  *
  * Step size: a constant tau, a given schedule tau_n, or backtracking on
  * L = 1/tau: starting from L_{n-1}, accept the trial p = P(Y - grad/L) when
@@ -412,7 +435,7 @@ int fcref_solve(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
     int completed = 0, failed = 0;
     int32_t reason = FCREF_STOP_MAXITER;
     for (int it = 1; it <= opt->max_iter; ++it) {
-        /* basic GPA step at Y_n */
+        /* projected gradient step at Y_n */
         fcref_x_s(n, row_ptr, col_idx, val, diag_unit, C, Y, YS);
         fcref_share(n, C, Y, share);
         gradient_from_parts(n, C, share, Y, YS, grad);

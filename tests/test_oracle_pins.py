@@ -121,7 +121,7 @@ def test_rows_subset_product_and_step_match_dense_definitions(O, diag_unit):
 
 
 # --------------------------------------------------------------------------
-# projection onto the simplex (Alg. 1)
+# projection onto the simplex (section 2; Alg. 1 computes the same point)
 # --------------------------------------------------------------------------
 
 def _kkt_ok(v, y, tol=1e-12):
@@ -167,6 +167,30 @@ def test_projection_special_cases(O):
     P = O.project_columns(V)
     for i in range(20):
         assert np.abs(P[i] - pins.project_simplex_bruteforce(V[i])).max() <= 1e-13
+
+
+def test_projection_extreme_scales_and_wide_rows(O):
+    """Offsets far from zero, tiny spreads, exact simplex points with zero
+    components and rows up to 64 wide: the KKT conditions hold, and the
+    result is unchanged by a constant shift (section 2: the projection
+    ignores multiples of the ones vector)."""
+    rng = np.random.default_rng(41)
+    for c in (4, 17, 32, 64):
+        for trial in range(60):
+            v = rng.normal(size=c) * [1e-9, 1e-3, 1.0, 1e3][trial % 4]
+            shift = [0.0, 1e6, -1e6, 0.25][(trial // 4) % 4]
+            y = O.project_simplex(v + shift)
+            tol = 1e-12 * max(1.0, abs(shift))
+            assert _kkt_ok(v + shift, y, tol=tol), (c, trial)
+            if shift == 0.0:
+                y0 = O.project_simplex(v)
+                assert np.abs(y0 - O.project_simplex(v + 0.375)).max() <= 1e-13
+    # an exact point of the simplex with zero components is its own projection
+    x = np.zeros(8)
+    x[[1, 4, 6]] = [0.5, 0.25, 0.25]
+    assert np.array_equal(O.project_simplex(x), x)
+    # equal components share the mass equally
+    assert np.allclose(O.project_simplex(np.full(5, 3.0)), 0.2, rtol=0, atol=1e-15)
 
 
 # --------------------------------------------------------------------------
@@ -464,6 +488,71 @@ def test_pgrad_stop_rule(O):
     assert res.stop_reason == O.STOP_PGRAD
     assert res.r[-1] <= 1e-2 * res.r[1]
     assert (res.r[1:-1] > 1e-2 * res.r[1]).all()
+
+
+# --------------------------------------------------------------------------
+# the gradient-mapping norm r_n (the paper defines no such measure; it is read
+# as the length of the projected-gradient step taken at Y_n, over tau_n)
+# --------------------------------------------------------------------------
+
+def _fd_gradient_cn(S, Y):
+    """Gradient of f at Y (C x N) by central differences of the double-sum
+    objective, in the C x N orientation."""
+    return pins.central_difference_gradient(S, Y.T.copy(), h=1e-5).T
+
+
+def test_pgrad_interior_step_has_the_tangent_gradient_norm(O):
+    """Closed form.  When the step from Y stays inside the simplex, the
+    projection only removes each row's mean, so Y - P(Y - tau grad) =
+    tau (grad - row means) and r_1 = ||grad f(Y) (I - 11^T/c)||_F for every
+    small tau.  The gradient here comes from central differences of the
+    objective's definition, not from any formula of the oracle."""
+    rng = np.random.default_rng(43)
+    n, c = 8, 3
+    (rp, ci, v), _ = pins.random_symmetric_csr(n, 0.5, rng)
+    S = pins.dense_similarity(rp, ci, v, True, n)
+    X0 = 0.25 / c + 0.75 * pins.random_simplex_rows(n, c, rng)   # entries >= 1/(4c)
+    g = pins.central_difference_gradient(S, X0, h=1e-5)          # N x C rows
+    tangent = g - g.mean(axis=1, keepdims=True)
+    want = float(np.sqrt((tangent ** 2).sum()))
+    for tau in (1e-5, 3e-5):
+        assert (X0 - tau * g).min() > 0        # the step stays interior
+        for accelerate in (False, True):
+            res = O.solve(rp, ci, v, True, X0, accelerate=accelerate, max_iter=1, step=tau)
+            assert res.r[1] == pytest.approx(want, rel=1e-7), (tau, accelerate)
+
+
+@pytest.mark.parametrize("mode", ["gpa", "fista", "backtrack"])
+def test_pgrad_norm_follows_its_definition_along_the_run(O, mode):
+    """r_n = ||Y_n - P_Omega(Y_n - tau_n grad f(Y_n))||_F / tau_n at every
+    iteration, with Y_n, the gradient (finite differences of the objective's
+    definition) and the projection (support enumeration) all formed
+    independently of the oracle; and the relative stop fires at the first n
+    with r_n <= tol r_1."""
+    rng = np.random.default_rng(47)
+    n, c = 9, 3
+    (rp, ci, v), _ = pins.random_symmetric_csr(n, 0.5, rng)
+    S = pins.dense_similarity(rp, ci, v, True, n)
+    X0 = pins.random_simplex_rows(n, c, rng)
+    kw = dict(max_iter=10)
+    if mode == "backtrack":
+        kw.update(backtrack=True, L0=0.05)
+    else:
+        kw.update(step=0.02)
+    res = O.solve(rp, ci, v, True, X0, accelerate=mode != "gpa", **kw)
+    Ys = []
+    _dense_iterations(S, X0, res.tau[1:], 10, mode != "gpa", points=Ys)
+    for it in range(1, 11):
+        Y, tau = Ys[it - 1], res.tau[it]
+        Xbar = _dense_project(Y - tau * _fd_gradient_cn(S, Y))
+        r_def = float(np.sqrt(((Y - Xbar) ** 2).sum())) / tau
+        assert res.r[it] == pytest.approx(r_def, rel=1e-6), it
+    # the stop fires at the first iteration that meets the relative test
+    tol = float(res.r[6] / res.r[1]) * 1.0000001
+    first = next(k for k in range(1, 11) if res.r[k] <= tol * res.r[1])
+    stopped = O.solve(rp, ci, v, True, X0, accelerate=mode != "gpa", tol_pgrad=tol, **kw)
+    assert stopped.stop_reason == O.STOP_PGRAD
+    assert stopped.iters == first
 
 
 # --------------------------------------------------------------------------
