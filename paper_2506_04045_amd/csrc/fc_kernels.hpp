@@ -28,6 +28,8 @@
 
 #include <type_traits>
 
+#include "fc_host.hpp"
+
 namespace fc {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -405,10 +407,12 @@ __global__ __launch_bounds__(256) void k_sumsq<double>(const double *__restrict_
 }
 
 // ---------------------------------------------------------------------------
-// CSR validation: row_ptr monotone from 0 to nnz, columns in range, and
-// (diag_unit) no stored diagonal.  Symmetry is checked by k_check_symmetry:
-// for every stored (i, j, s) the row j must store (j, i) with the same value
-// (binary search; rows must be sorted for that check).
+// CSR validation of the stored entries, launched only after the host has
+// checked row_ptr (starts at 0, never decreases, ends at nnz), so every row
+// range below lies in [0, nnz).  Flags: 2 a column out of range, 4 a stored
+// diagonal in unit-diagonal mode, 8 a row not sorted or with a duplicate
+// column, 16 an entry (i, j, s) whose mirror (j, i) is missing or holds
+// another value (binary search in row j; needs sorted rows).
 // ---------------------------------------------------------------------------
 template <typename VS>
 __global__ void k_check_csr(const int64_t *__restrict__ row_ptr, const int32_t *__restrict__ col,
@@ -417,10 +421,6 @@ __global__ void k_check_csr(const int64_t *__restrict__ row_ptr, const int32_t *
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const int64_t b = row_ptr[i], e = row_ptr[i + 1];
-        if (b > e || b < 0 || e > nnz || (i == 0 && b != 0) || (i == n - 1 && e != nnz)) {
-            atomicOr(&flags[0], 1);
-            continue;
-        }
         for (int64_t k = b; k < e; ++k) {
             const int32_t j = col[k];
             if (j < 0 || j >= n) {
@@ -432,7 +432,10 @@ __global__ void k_check_csr(const int64_t *__restrict__ row_ptr, const int32_t *
             if (k > b && col[k - 1] >= j)
                 atomicOr(&flags[0], 8);  // unsorted or duplicate: symmetry check unavailable
             if (check_sym) {
+                // clamped to the stored range as well, so no read leaves it
                 int64_t lo = row_ptr[j], hi = row_ptr[j + 1] - 1;
+                lo = lo < 0 ? 0 : lo;
+                hi = hi > nnz - 1 ? nnz - 1 : hi;
                 bool found = false;
                 while (lo <= hi) {
                     const int64_t mid = (lo + hi) >> 1;
@@ -490,7 +493,6 @@ template <typename TU, int CP, int WANT_SLOTS> struct TeamCfg {
 // Short rows (at most SPMM_LIGHT_MAX nonzeros, most rows of a sparse graph)
 // get two-slot teams, so a wave works on several rows at once; longer rows
 // get whole waves of eight slots.
-constexpr int SPMM_LIGHT_MAX = 64;
 template <typename TU, int CP> struct SpmmCfg {
     using Light = TeamCfg<TU, CP, 2>;
     using Wide = TeamCfg<TU, CP, 8>;

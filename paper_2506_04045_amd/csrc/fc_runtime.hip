@@ -32,6 +32,7 @@
 #include <hipcub/device/device_scan.hpp>
 
 #include "fc.h"
+#include "fc_host.hpp"
 #include "fc_kernels.hpp"
 #include "fc_second.hpp"
 
@@ -114,12 +115,6 @@ void launch_reduce(const double *in, int64_t np, int64_t ld, int64_t ne, double 
     hipLaunchKernelGGL(k_reduce_cols, dim3(blocks), dim3(256), 0, s, in, np, ld, ne, out, eb);
 }
 
-// Rows with more than SPMM_LIGHT_MAX nonzeros are summed by whole-wave teams:
-// up to HEAVY_THR directly (the medium-row list), beyond it in chunks of
-// HEAVY_CHUNK nonzeros combined per row in chunk order.
-constexpr int64_t HEAVY_THR = 2048;
-constexpr int64_t HEAVY_CHUNK = 1024;
-
 // Heavy-row plan built on the host from row_ptr.  Device arrays are owned
 // by `bufs` (stream-ordered frees).
 struct HeavyPlan {
@@ -151,26 +146,10 @@ fc_status build_heavy_plan(const int64_t *d_row_ptr, int64_t n, size_t acc_bytes
     std::vector<int64_t> rp(n + 1);
     HIPCHK(hipMemcpyAsync(rp.data(), d_row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    std::vector<int32_t> rows, cptr, crow, clen, med;
-    std::vector<int64_t> cbeg;
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t len = rp[i + 1] - rp[i];
-        if (len <= SPMM_LIGHT_MAX)
-            continue;
-        if (len <= HEAVY_THR) {
-            med.push_back((int32_t)i);
-            continue;
-        }
-        rows.push_back((int32_t)i);
-        cptr.push_back((int32_t)cbeg.size());
-        for (int64_t b = rp[i]; b < rp[i + 1]; b += HEAVY_CHUNK) {
-            const int64_t l = rp[i + 1] - b < HEAVY_CHUNK ? rp[i + 1] - b : HEAVY_CHUNK;
-            crow.push_back((int32_t)i);
-            cbeg.push_back(b);
-            clen.push_back((int32_t)l);
-        }
-    }
-    cptr.push_back((int32_t)cbeg.size());
+    HeavyRows hr = plan_heavy_rows(rp.data(), n);
+    const std::vector<int32_t> &rows = hr.rows, &cptr = hr.chunk_ptr, &crow = hr.chunk_row,
+                               &clen = hr.chunk_len, &med = hr.med;
+    const std::vector<int64_t> &cbeg = hr.chunk_beg;
     plan.nheavy = (int64_t)rows.size();
     plan.nchunks = (int64_t)cbeg.size();
     plan.nmed = (int64_t)med.size();
@@ -836,6 +815,20 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
     hipStream_t s = h->stream;
 
     if (opt->validate) {
+        // row_ptr on the host first: the entry checks below index rows by it
+        std::vector<int64_t> rp(S->n + 1);
+        if (hipMemcpyAsync(rp.data(), S->row_ptr, sizeof(int64_t) * (S->n + 1), hipMemcpyDeviceToHost,
+                           s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return cleanup(fail(FC_ERR_DEVICE, "validation: row_ptr readback"));
+        int64_t bad = 0;
+        const int rpc = check_row_ptr(rp.data(), S->n, S->nnz, &bad);
+        if (rpc != RP_OK)
+            return cleanup(fail(FC_ERR_NOT_SYMMETRIC,
+                                std::string("CSR structure invalid: row_ptr ") +
+                                    (rpc == RP_FIRST ? "does not start at 0"
+                                     : rpc == RP_DECREASING ? "decreases after row " + std::to_string(bad)
+                                                            : "does not end at nnz")));
         int32_t *flags = nullptr;
         if (h->alloc(&flags, sizeof(int32_t)) != hipSuccess)
             return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "validation buffer"));
@@ -858,8 +851,8 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
         if (hipMemcpyAsync(&hf, flags, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return cleanup(fail(FC_ERR_DEVICE, "validation readback"));
-        if (hf & 3)
-            return cleanup(fail(FC_ERR_NOT_SYMMETRIC, "CSR structure invalid (row_ptr or col_idx out of range)"));
+        if (hf & 2)
+            return cleanup(fail(FC_ERR_NOT_SYMMETRIC, "CSR structure invalid: col_idx out of range"));
         if (hf & 4)
             return cleanup(fail(FC_ERR_INVALID_ARG, "FC_DIAG_UNIT requires no stored diagonal entries"));
         if (hf & 8)
@@ -895,19 +888,10 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
         h->alloc(&h->d_GYs, esz * h->cpm * h->cpm) != hipSuccess)
         return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "solver state"));
 
-    // launch geometry: persistent grids sized to the device
+    // launch geometry: persistent grids sized to the device (the fused
+    // kernel's count by the rule served instances share)
     const int cus = device_cus();
-    // one row tile per workgroup up to 2 workgroups per CU; large single
-    // solves up to 32 per CU while keeping at least 8 tiles per workgroup
-    // (n = 7e7, c = 32: 8.6 ms for the fused pass and 0.13 ms for reducing
-    // its partials, against 8.9 and 0.05 ms at 12 per CU); served instances
-    // stay at 2 per CU
-    {
-        int64_t cap = (int64_t)cus * 2;
-        if (!pooled)
-            cap = std::min<int64_t>((int64_t)cus * 32, std::max<int64_t>(cap, h->n / 512));
-        h->g_fused = grid_1d(h->n, 64, cap);
-    }
+    h->g_fused = (int)fused_grid(h->n, cus);
     h->g_gram = grid_1d(cdiv(h->n, 16), 4, (int64_t)cus * 2);
     {
         int rows_per_wg = 1;

@@ -187,3 +187,22 @@ def test_tuned_schedule_keeps_every_result(fc):
         assert r.status == 0
         assert r.f == info.f and r.iter == info.iter
         assert np.array_equal(U, U_ref)
+
+
+def test_large_request_sums_as_it_does_alone(fc):
+    """An instance above two fused workgroups per CU of 64-row tiles with
+    eight tiles each (n > 2 * CUs * 512) gets more fused workgroups; served
+    and solo solves use the same count, so the result stays bitwise equal."""
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    n = 2 * cus * 512 + 40_000
+    big = W.er_planted(n, 4, 6.0, 0.05, 1300).to("cuda")
+    small = _requests(3, seed0=1400)
+    kw = dict(max_iter=30)
+    alone = [_alone(fc, wl, **kw) for wl in [big] + small]
+    served = _serve(fc, [big] + small, dict(ticks_per_poll=4), **kw)
+    for i in range(4):
+        r, U = served[i]
+        info, U_ref = alone[i]
+        assert r.status == 0 and r.iter == info.iter
+        assert r.f == info.f, (i, r.f, info.f)
+        assert np.array_equal(U, U_ref), i

@@ -266,6 +266,21 @@ def test_validation_rejects_bad_matrices(fc):
     with fc.Solver(*csr_to_dev(rp, ci, v, torch.float32), 2, None, validate=True, diag="stored",
                    step=0.1) as s:
         assert s.step(2).iter == 2
+    # malformed structure: row_ptr is checked on the host before any entry is
+    # read, so none of these reaches the device's entry checks
+    C = np.array([[0, 1, 1], [1, 0, 1], [1, 1, 0]], dtype=float)
+    rp, ci, v = pins.csr_from_dense(C)
+    for bad_rp in ([0, 2, 1_000_000_000, 6], [0, 3, 2, 6], [1, 2, 4, 6], [0, 2, 4, 5]):
+        Sd = csr_to_dev(np.array(bad_rp, dtype=np.int64), ci, v, torch.float32)
+        with pytest.raises(_native.FcError) as e:
+            fc.Solver(*Sd, 2, None, validate=True, step=0.1)
+        assert e.value.status == _native.FC_ERR_NOT_SYMMETRIC, bad_rp
+        assert "row_ptr" in str(e.value)
+    bad_ci = ci.copy()
+    bad_ci[3] = 7                                                      # column out of range
+    with pytest.raises(_native.FcError) as e:
+        fc.Solver(*csr_to_dev(rp, bad_ci, v, torch.float32), 2, None, validate=True, step=0.1)
+    assert e.value.status == _native.FC_ERR_NOT_SYMMETRIC and "col_idx" in str(e.value)
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
