@@ -278,6 +278,28 @@ fc_status fc_spectral_norm(const fc_csr *S, fc_diag diag, int32_t max_iter,
                            double rtol, void *stream, double *norm_out,
                            int32_t *iters_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the Gram
+ * matrix of fc_gram, G = U^T U, with no allocation of any kind.
+ *   U      device, n x c, row i at U + i * ld (ld >= c elements), FC_F64 or
+ *          FC_F32; read in place (no padded copy).
+ *   G_out  device, c x c doubles, row-major; written on `stream`.
+ * The call is asynchronous (it only enqueues kernels on `stream` and never
+ * synchronises).  Its partial sums live in a library-owned static device
+ * array of FC_GRAM_NOALLOC_SCRATCH_BYTES bytes (about 32 MiB) on each GPU the
+ * library runs on, held until the process ends: at most 1,024 wave partials
+ * of a 64 x 64 block plus the reduced block, which bounds the workgroups of
+ * the pass (every n and every c <= 64 fits).  Every call on one GPU shares
+ * that GPU's array, so calls that overlap on the same GPU (two streams, two
+ * threads) race: serialise them, e.g. on one stream.  Each call overwrites
+ * all the scratch it reads, so no clearing is needed between calls.  The
+ * result equals fc_gram's to rounding (the per-tile sums are the same; the
+ * cross-tile order may differ for large n).  Errors: FC_ERR_INVALID_ARG
+ * (NULL pointers, n < 1, c outside [1, 64], ld < c, dtype), FC_ERR_DEVICE. */
+#define FC_GRAM_NOALLOC_SCRATCH_BYTES 33587200
+fc_status fc_gram_noalloc(const void *U, fc_dtype dtype, int64_t n, int32_t c, int64_t ld,
+                          void *stream, double *G_out);
+
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *fc_last_error(void);
 

@@ -19,7 +19,7 @@ import torch
 
 from . import _native as N
 
-__all__ = ["Solver", "Server", "Info", "objective", "project", "spmm", "gram", "spectral_norm",
+__all__ = ["Solver", "Server", "Info", "objective", "project", "spmm", "gram", "gram_noalloc", "spectral_norm",
            "library_path"]
 
 _PREC = {"fp64": N.FC_PREC_FP64, "fp32": N.FC_PREC_FP32, "mixed": N.FC_PREC_MIXED}
@@ -420,6 +420,25 @@ def gram(U: torch.Tensor, stream=None) -> np.ndarray:
     N.check(N.load().fc_gram(U.data_ptr(), _DT[U.dtype], n, c, _stream_ptr(stream),
                              G.ctypes.data))
     return G
+
+
+def gram_noalloc(U: torch.Tensor, G_out: torch.Tensor, stream=None) -> torch.Tensor:
+    """G_out = U^T U (fc_gram_noalloc): U (n x c, any row stride) read in
+    place, G_out a caller-owned c x c float64 device tensor; asynchronous,
+    allocates nothing."""
+    if not isinstance(U, torch.Tensor) or not U.is_cuda:
+        raise TypeError("U must be a CUDA (HIP) tensor")
+    if U.dtype not in (torch.float64, torch.float32):
+        raise TypeError(f"U has dtype {U.dtype}, expected float64 or float32")
+    if U.dim() != 2 or U.stride(1) != 1 or U.stride(0) < U.shape[1]:
+        raise ValueError("U must be 2-D with unit column stride and row stride >= c")
+    n, c = U.shape
+    if (G_out.device.type != "cuda" or G_out.dtype != torch.float64
+            or tuple(G_out.shape) != (c, c) or not G_out.is_contiguous()):
+        raise ValueError("G_out must be a contiguous c x c float64 CUDA tensor")
+    N.check(N.load().fc_gram_noalloc(U.data_ptr(), _DT[U.dtype], n, c, U.stride(0),
+                                     _stream_ptr(stream), G_out.data_ptr()))
+    return G_out
 
 
 def spectral_norm(row_ptr, col_idx, val, diag: str = "unit", max_iter: int = 1000,

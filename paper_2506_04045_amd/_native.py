@@ -32,6 +32,7 @@ EXPORTED = [
     "fc_server_opts_default", "fc_server_clock", "fc_server_create", "fc_server_submit",
     "fc_server_poll", "fc_server_get_u", "fc_server_release", "fc_server_stats",
     "fc_server_destroy", "fc_server_tune", "fc_hessian_vector", "fc_curvature",
+    "fc_gram_noalloc",
 ]
 
 
@@ -128,6 +129,8 @@ def load() -> ctypes.CDLL:
     lib.fc_spmm.restype = st
     lib.fc_gram.argtypes = [P, ctypes.c_int, i64, i32, P, P]
     lib.fc_gram.restype = st
+    lib.fc_gram_noalloc.argtypes = [P, ctypes.c_int, i64, i32, i64, P, P]
+    lib.fc_gram_noalloc.restype = st
     lib.fc_spectral_norm.argtypes = [ctypes.POINTER(CSR), ctypes.c_int, i32, f64, P,
                                      ctypes.POINTER(f64), ctypes.POINTER(i32)]
     lib.fc_spectral_norm.restype = st

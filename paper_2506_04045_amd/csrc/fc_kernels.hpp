@@ -904,9 +904,10 @@ template <int M> struct SymBlocks {
     }
 };
 
+// Rows of X have stride ldx and cx valid components (the rest count as zero).
 template <typename T, int CP>
-__global__ __launch_bounds__(256) void k_gram(const T *__restrict__ X, int64_t n,
-                                              double *__restrict__ part, int64_t ld) {
+__device__ __forceinline__ void gram_body(const T *__restrict__ X, int64_t ldx, int cx, int64_t n,
+                                          double *__restrict__ part, int64_t ld) {
     constexpr int CPM = CP < 16 ? 16 : CP;
     constexpr int M = CPM / 16;
     constexpr int NB = SymBlocks<M>::N;
@@ -927,7 +928,7 @@ __global__ __launch_bounds__(256) void k_gram(const T *__restrict__ X, int64_t n
 #pragma unroll
             for (int a = 0; a < M; ++a) {
                 const int k = 16 * a + r;
-                xv[t][a] = (row < n && k < CP) ? X[row * CP + k] : (T)0;
+                xv[t][a] = (row < n && k < CP && k < cx) ? X[row * ldx + k] : (T)0;
             }
         }
 #pragma unroll
@@ -956,6 +957,29 @@ __global__ __launch_bounds__(256) void k_gram(const T *__restrict__ X, int64_t n
                 out[j * CPM + i] = acc64[kb][q];
         }
     }
+}
+
+// Padded rows (stride CP, padding zero): the solver's iterates.
+template <typename T, int CP>
+__global__ __launch_bounds__(256) void k_gram(const T *__restrict__ X, int64_t n,
+                                              double *__restrict__ part, int64_t ld) {
+    gram_body<T, CP>(X, CP, CP, n, part, ld);
+}
+
+// A caller's matrix read in place: rows of stride ldx with cx components.
+template <typename T, int CP>
+__global__ __launch_bounds__(256) void k_gram_strided(const T *__restrict__ X, int64_t ldx, int cx,
+                                                      int64_t n, double *__restrict__ part,
+                                                      int64_t ld) {
+    gram_body<T, CP>(X, ldx, cx, n, part, ld);
+}
+
+// out[i * c + j] = in[i * ld + j] for i, j < c (the c x c corner of a padded
+// matrix, in place of a strided copy).
+__global__ void k_corner_copy(const double *__restrict__ in, int ld, int c,
+                              double *__restrict__ out) {
+    for (int e = threadIdx.x; e < c * c; e += blockDim.x)
+        out[e] = in[(e / c) * ld + e % c];
 }
 
 // ---------------------------------------------------------------------------

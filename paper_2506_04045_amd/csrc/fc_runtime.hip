@@ -1583,6 +1583,95 @@ fc_status fc_gram(const void *U, fc_dtype dtype, int64_t n, int32_t c, void *str
     return FC_OK;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free Gram matrix.  Its partial sums live in one static device
+// array per GPU; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's own name is a host
+// stand-in there).  Calls on one GPU share the array, so calls that overlap
+// on the same GPU race.
+// ---------------------------------------------------------------------------
+namespace {
+
+constexpr int NOALLOC_MAX_WG = 256;                    // workgroups of the Gram pass
+constexpr int64_t NOALLOC_PARTS = 4 * NOALLOC_MAX_WG;  // one partial per wave
+constexpr int64_t NOALLOC_MAT = 64 * 64;               // largest padded c x c block
+constexpr int64_t NOALLOC_WORDS = NOALLOC_PARTS * NOALLOC_MAT + NOALLOC_MAT;
+static_assert(NOALLOC_WORDS * 8 == FC_GRAM_NOALLOC_SCRATCH_BYTES,
+              "fc.h states the scratch size");
+
+static __device__ __align__(256) double scratch[NOALLOC_WORDS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[MAX_DEVICES] = {};
+
+// The array's device address on the current device, looked up once per device.
+fc_status scratch_on_current_device(double **out) {
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES)
+        return fail(FC_ERR_UNSUPPORTED, "device index beyond the library's table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p)
+            return fail(FC_ERR_DEVICE, "hipGetSymbolAddress returned no address for the scratch array");
+        g_scratch_ptr[dev] = (double *)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fc_status fc_gram_noalloc(const void *U, fc_dtype dtype, int64_t n, int32_t c, int64_t ld,
+                          void *stream, double *G_out) {
+    g_last_error.clear();
+    if (!U || !G_out)
+        return fail(FC_ERR_INVALID_ARG, "U or G_out is NULL");
+    if (n < 1 || c < 1 || c > 64 || ld < c)
+        return fail(FC_ERR_INVALID_ARG, "need n >= 1, c in [1, 64] and ld >= c");
+    if (dtype != FC_F64 && dtype != FC_F32)
+        return fail(FC_ERR_INVALID_ARG, "dtype must be FC_F64 or FC_F32");
+    const int cp = cp_of(c);
+    const int cpm = cpm_of(cp);
+    const int64_t mat = (int64_t)cpm * cpm;
+    const int cus = device_cus();
+    // the grid of fc_gram, capped so that the partials fit the scratch array
+    const int g = grid_1d(cdiv(n, 16), 4, std::min<int64_t>((int64_t)cus * 2, NOALLOC_MAX_WG));
+    if ((int64_t)g * 4 * mat + mat > NOALLOC_WORDS)
+        return fail(FC_ERR_INVALID_ARG, "partial sums exceed the scratch array");
+    double *base = nullptr;
+    fc_status st = scratch_on_current_device(&base);
+    if (st != FC_OK)
+        return st;
+    double *part = base, *red = base + NOALLOC_PARTS * NOALLOC_MAT;
+    hipStream_t s = (hipStream_t)stream;
+    st = with_cp(cp, [&](auto cpc) -> fc_status {
+        constexpr int CP = decltype(cpc)::value;
+        if (dtype == FC_F64)
+            hipLaunchKernelGGL((k_gram_strided<double, CP>), dim3(g), dim3(256), 0, s,
+                               (const double *)U, ld, c, n, part, mat);
+        else
+            hipLaunchKernelGGL((k_gram_strided<float, CP>), dim3(g), dim3(256), 0, s,
+                               (const float *)U, ld, c, n, part, mat);
+        HIPCHK(hipGetLastError());
+        return FC_OK;
+    });
+    if (st != FC_OK)
+        return st;
+    // every wave writes its whole partial block, so nothing needs clearing
+    launch_reduce(part, (int64_t)g * 4, mat, mat, red, s);
+    hipLaunchKernelGGL(k_corner_copy, dim3(1), dim3(256), 0, s, (const double *)red, cpm, c, G_out);
+    HIPCHK(hipGetLastError());
+    return FC_OK;
+}
+
 fc_status fc_project(const void *V, void *out, fc_dtype dtype, int64_t rows, int32_t c, int64_t ld,
                      void *stream) {
     g_last_error.clear();
