@@ -34,7 +34,7 @@ def fc():
     return fc
 
 
-def _check_first_step(fc, wl, precision, val_for_oracle, seed, reorders=("degree",)):
+def _check_first_step(fc, wl, precision, val_for_oracle, seed, configs=(("degree", True),)):
     rows = _sample(wl.row_ptr, seed)
     sub_rp, sub_ci, sub_v = _sub_csr(wl.row_ptr, wl.col_idx, wl.val, rows)
     if val_for_oracle is not None:
@@ -53,19 +53,20 @@ def _check_first_step(fc, wl, precision, val_for_oracle, seed, reorders=("degree
         assert err <= 1e-5
 
     # one step in the benchmark's launch configuration (articles relabelled by
-    # degree inside the solver), and without relabelling
+    # degree inside the solver, deferred loss evaluation), and in the plain one
     x_ref = oracle.step_rows(rows, sub_rp, sub_ci, sub_v, True, U0, TAU)
     moved = np.abs(x_ref - U0[rows]).max()
-    for reorder in reorders:
+    for reorder, defer in configs:
         with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, precision=precision,
-                       accelerate=True, step=TAU, reorder=reorder) as s:
+                       accelerate=True, step=TAU, reorder=reorder, defer_loss=defer) as s:
             s.step(1)
             U1 = s.get_u()
             x_gpu = U1[torch.from_numpy(rows).cuda()].double().cpu().numpy()
             del U1
         du = np.abs(x_gpu - x_ref).max()
-        print(f"full-size first step ({precision}, relabelling {reorder}), {rows.size} sampled "
-              f"rows: max|dU| {du:.2e} (the step moves entries by up to {moved:.2e})")
+        print(f"full-size first step ({precision}, relabelling {reorder}, deferred loss "
+              f"{defer}), {rows.size} sampled rows: max|dU| {du:.2e} (the step moves entries "
+              f"by up to {moved:.2e})")
         # FP32 iterates of magnitude <= 1 carry ulps of at most 6e-8; the
         # step itself moves entries by about 4 tau n u_k / (c (c + 1)) ~ 1e-5
         assert du <= (1e-7 if precision == "fp32" else 5e-7)
@@ -75,12 +76,12 @@ def _check_first_step(fc, wl, precision, val_for_oracle, seed, reorders=("degree
 def test_power_law_full_size_fp32(fc):
     wl = W.config_full_power_law(device="cuda")
     torch.cuda.synchronize()
-    _check_first_step(fc, wl, "fp32", None, seed=1, reorders=("degree", "none"))
+    _check_first_step(fc, wl, "fp32", None, seed=1, configs=(("degree", True), ("none", False)))
 
     # later iterations: simplex columns and bitwise-identical reruns
     def run(k):
         with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, accelerate=True,
-                       step=0.0, reorder="degree") as s:
+                       step=0.0, reorder="degree", defer_loss=True) as s:
             info = s.step(k)
             return info, s.get_u()
     info_a, Ua = run(12)

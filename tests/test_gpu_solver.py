@@ -5,8 +5,9 @@ Tolerances (stated in the fuzzy-clustering workload's parity bar):
 * FP64 on the GPU follows the oracle to rounding: per-iteration losses within
   1e-9 relative, iterates within 1e-9.
 * FP32 on the GPU against the FP64 oracle: final loss within 1e-4 relative,
-  the loss decrease f(U0) - f(U_K) within 1e-3 relative, iterates within
-  1e-4, rows summing to 1 within 1e-6.
+  the loss decrease f(U0) - f(U_K) within 1e-5 relative (the loss is
+  dominated by ||G||^2 ~ n^2/c^2, which hides the decrease, so the decrease is
+  checked on its own), iterates within 1e-4, rows summing to 1 within 1e-6.
 """
 import json
 import math
@@ -82,7 +83,7 @@ def test_small_fp32_against_fp64_oracle(fc, small, defer):
     print(f"fp32 small: f_rel={f_rel:.2e} df_rel={df_rel:.2e} "
           f"max|dU|={np.abs(U - ref.X).max():.2e}")
     assert f_rel <= 1e-4
-    assert df_rel <= 1e-3
+    assert df_rel <= 1e-5
     assert np.abs(U - ref.X).max() <= 1e-4
     assert np.abs(U.sum(1) - 1).max() <= 1e-6
     assert (U >= 0).all()
@@ -409,25 +410,53 @@ def test_degree_relabelling_with_hub_rows_and_empty_rows(fc):
     assert abs(info.f - ref.f[-1]) <= 1e-9 * abs(ref.f[-1])
 
 
-def test_medium_config_replays_backtracking_fp32(fc):
-    """The n = 1e6, c = 32 configuration (ER degree 30, 3e7 nonzeros):
-    backtracking FISTA in the oracle, its accepted steps replayed by the FP32
-    solver (a few iterations: the oracle takes about a second per trial)."""
+def test_medium_config_replays_500_backtracking_iterations_fp32(fc):
+    """The n = 1e6, c = 32 configuration (ER degree 30, 3e7 nonzeros) over its
+    500 iterations: the FP64 oracle's run of backtracking FISTA (stored by
+    tests/golden/make_medium_replay.py, which calls only the oracle and the
+    workload generator) replayed by the FP32 solver through its accepted
+    steps.  The whole loss history, the decrease, Xbar_500 at the stored
+    sample rows and the row sums are compared."""
+    from tests.golden.make_medium_replay import OUT, fingerprint
+    gold = json.load(open(OUT))
     wl = W.config_medium(seed=0)
     rp, ci, v, U0 = wl.numpy()
-    assert wl.nnz > 29_000_000
-    ref = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=6, backtrack=True,
-                       L0=1e4)
-    assert ref.trials[1:].sum() > 6          # at least one rejected trial
-    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, 32, "fp32", 6, step_schedule=ref.tau[1:])
-    f_rel = abs(info.f - ref.f[-1]) / abs(ref.f[-1])
-    df = ref.f[0] - ref.f[-1]
+    assert fingerprint(rp, ci, v, U0) == gold["instance"], "the seeded instance changed"
+    K = gold["iters"]
+    tau = np.asarray(gold["tau"])
+    f_ref = np.asarray(gold["f"])
+    assert K == 500 and sum(gold["trials"]) > K      # rejected trials happened
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, 32, "fp32", K, step_schedule=tau)
+    assert info.iter == K
+    rows = np.asarray(gold["rows"])
+    X_ref = np.asarray(gold["X_rows"])
+    f_hist_rel = np.abs(hist["f"] - f_ref).max() / abs(f_ref[-1])
+    df = f_ref[0] - f_ref[-1]
     df_rel = abs((hist["f"][0] - info.f) - df) / abs(df)
-    du = np.abs(U - ref.X).max()
-    print(f"medium replay fp32: f_rel={f_rel:.2e} df_rel={df_rel:.2e} max|dU|={du:.2e}")
-    assert f_rel <= 1e-4 and df_rel <= 1e-3 and du <= 1e-4
-    assert np.abs(U.sum(1) - 1).max() <= 1e-6
+    du = np.abs(U[rows] - X_ref).max()
+    print(f"medium replay fp32, {K} iterations: f history rel {f_hist_rel:.2e} "
+          f"df_rel={df_rel:.2e} (df={df:.6e}) max|dU| on {rows.size} rows {du:.2e}")
+    assert f_hist_rel <= 1e-4
+    assert df_rel <= 1e-5
+    assert du <= 1e-4
+    assert np.abs(U.sum(1) - 1).max() <= 1e-6 and (U >= 0).all()
 
+
+def test_medium_config_backtracking_decisions_fp64(fc):
+    """The same instance in FP64, free-running: the device's backtracking takes
+    the oracle's decisions (trials and accepted steps) over the first 40 stored
+    iterations."""
+    from tests.golden.make_medium_replay import OUT
+    gold = json.load(open(OUT))
+    wl = W.config_medium(seed=0)
+    rp, ci, v, U0 = wl.numpy()
+    K = 40
+    info, U, hist = _solve_gpu(fc, rp, ci, v, U0, 32, "fp64", K, backtrack=True,
+                               L0=gold["L0"])
+    assert (hist["trials"][1:] == np.asarray(gold["trials"][:K])).all()
+    assert np.array_equal(hist["tau"][1:], np.asarray(gold["tau"][:K]))
+    f_ref = np.asarray(gold["f"][:K + 1])
+    assert np.abs(hist["f"] - f_ref).max() <= 1e-9 * abs(f_ref[0])
 
 
 # --------------------------------------------------------------------------
