@@ -70,32 +70,168 @@ def measured_traffic(kernel: str, workload_key: str):
     return ent.get("hbm_bytes_per_launch")
 
 
+def degree_relabelled_columns(row_ptr, col_idx, chunk_rows: int = 1 << 23):
+    """The column sequence the relabelled solver's product walks: rows in
+    descending-degree order (ties by index), each row's nonzeros in their
+    stored order, columns renumbered the same way (torch, on the GPU)."""
+    import torch
+    n = row_ptr.numel() - 1
+    deg = row_ptr[1:] - row_ptr[:-1]
+    perm = torch.sort(-deg, stable=True).indices
+    inv = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
+    inv[perm] = torch.arange(n, dtype=torch.int32, device=row_ptr.device)
+    out = torch.empty_like(col_idx)
+    pos = 0
+    for a in range(0, n, chunk_rows):
+        rows = perm[a:a + chunk_rows]
+        lens = deg[rows]
+        total = int(lens.sum())
+        if total == 0:
+            continue
+        first = torch.cumsum(lens, 0) - lens
+        src = (row_ptr[rows] - first).repeat_interleave(lens, output_size=total)
+        src += torch.arange(total, device=row_ptr.device)
+        out[pos:pos + total] = inv[col_idx[src].long()]
+        pos += total
+        del src, lens, first
+    del perm, deg
+    return out, inv
+
+
+def gather_ceiling(args, wl, c: int) -> dict:
+    """The memory system's rate on the sparse product's gathers: a flat pass
+    that only gathers row col[e] of an n x c matrix for every stored nonzero
+    (fc_gather_probe; no values, no products, no output), on the relabelled
+    solver's column sequence, on the generator's order, and on uniformly
+    random columns (no reuse); rows of FP32 (128 B at c = 32) and of bfloat16
+    (64 B).  Best of three launch shapes each."""
+    import torch
+    import paper_2506_04045_amd as fc
+    n = wl.n
+    log("gather ceiling: relabelling the column sequence")
+    col_rel, _ = degree_relabelled_columns(wl.row_ptr, wl.col_idx)
+    U32 = torch.rand(n, c, device="cuda", dtype=torch.float32)
+    out = {"what": ("flat gather of row col[e] of an n x c matrix for every stored nonzero, "
+                    "16-byte lane loads, 4 gathers in flight per team, next indices loaded "
+                    "ahead; no values, products or output rows"), "runs": {}}
+
+    def best(col, U, name):
+        runs = {w: fc.gather_probe(col, U, wg_per_cu=w, reps=5) for w in (8, 16, 32)}
+        w = min(runs, key=runs.get)
+        rb = U.shape[1] * U.element_size()
+        out["runs"][name] = {"ms": runs[w], "wg_per_cu": w, "row_bytes": rb,
+                             "rows_per_s": wl.nnz / (runs[w] * 1e-3),
+                             "gathered_GBps": wl.nnz * rb / (runs[w] * 1e6),
+                             "ms_by_wg_per_cu": runs}
+        log(f"gather ceiling {name}: {runs[w]:.2f} ms ({wl.nnz * rb / (runs[w] * 1e6):.0f} GB/s "
+            f"of gathered rows, {w} workgroups per CU)")
+        return runs[w]
+
+    out["relabelled_fp32_ms"] = best(col_rel, U32, "relabelled_fp32")
+    best(wl.col_idx, U32, "generator_order_fp32")
+    Ub = U32.to(torch.bfloat16)
+    best(col_rel, Ub, "relabelled_bf16")
+    del Ub
+    rnd = torch.randint(0, n, (wl.nnz,), device="cuda", dtype=torch.int32,
+                        generator=torch.Generator(device="cuda").manual_seed(5))
+    best(rnd, U32, "uniform_random_fp32")
+    del rnd, col_rel, U32
+    torch.cuda.empty_cache()
+    return out
+
+
+def host_cpu() -> dict:
+    """The host's CPU model and core counts."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = None
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable,
+            "OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")}
+
+
+def _median_iteration(res) -> float:
+    """Median wall time of iterations 2..K of an oracle run."""
+    import numpy as np
+    secs = np.asarray(res.seconds[2:], dtype=float)
+    return float(np.median(secs[np.isfinite(secs)]))
+
+
 def cpu_baseline(args, c: int, n_full: int, nnz_full: int) -> dict:
-    """The FP64 oracle (plain C + OpenMP) timed for a few FISTA iterations on
-    a bounded sample: an instance of the same generator with fewer nodes, its
-    per-iteration time scaled to the full instance by the nonzero count."""
+    """The FP64 oracle (plain C + OpenMP, as committed) timed on the host
+    cores: the median wall time per iteration over iterations 2..K.
+
+    value: the headline workload's rate, extrapolated: K FISTA iterations
+    (constant step) on a bounded sample -- an instance of the same power-law
+    generator with fewer nodes -- scaled by the nonzero count to the full
+    instance.  Beside it, two of the family's configurations measured as they
+    are (no scaling): n = 2,000, c = 8 (200 FISTA iterations, tau = 1/L_thm)
+    and n = 1e6, c = 32 (K iterations of FISTA with backtracking, L0 =
+    L_thm/100).  The oracle applies S twice per iteration, as Alg. 4 is
+    printed (at Y_n for the gradient and at the new iterate for the loss; a
+    backtracking trial applies it once more), where the GPU path applies it
+    once."""
     import torch
     import oracle
     import workloads as W
     oracle.build(force=False)
-    ns = args.cpu_sample_n
-    log(f"cpu baseline: generating a {ns}-node sample instance on the host")
+    threads = oracle.num_threads()
+    out = {"unit": "iters/s", "cores": threads, "kind": "oracle", "host": host_cpu(),
+           "oracle_threads": threads, "sparse_products_per_iteration": {"oracle": 2, "gpu": 1}}
+
+    # the headline workload, extrapolated from a bounded sample
+    ns, K = args.cpu_sample_n, max(3, args.cpu_iters)
+    log(f"cpu baseline: {ns:,}-node power-law sample, {K} oracle iterations on {threads} threads")
     wl = W.chung_lu_planted(ns, c, 20.0, 2.1, 50_000.0, 0.05, 1, device="cpu")
     rp, ci, v, U0 = wl.numpy()
     spec, _ = oracle.spectral_norm(rp, ci, v, True, max_iter=200, rtol=1e-6)
     tau = 1.0 / oracle.lipschitz_bound(spec, ns)
-    iters = args.cpu_iters
-    log(f"cpu baseline: {iters} oracle iterations on {oracle.num_threads()} threads")
-    t0 = time.perf_counter()
-    oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=iters, step=tau)
-    dt = (time.perf_counter() - t0) / iters
+    res = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=K, step=tau, timed=True)
+    dt = _median_iteration(res)
     scale = nnz_full / max(1, wl.nnz)
-    del wl, rp, ci, v, U0
-    return {"value": 1.0 / (dt * scale), "unit": "iters/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": (f"FP64 oracle FISTA iterations ({iters}) on a {ns:,}-node instance of the "
-                       f"same power-law generator (c={c}, mean degree 20, exponent 2.1); "
-                       f"{dt:.3f} s/iteration scaled by nnz x{scale:.1f} to the full instance")}
+    out["value"] = 1.0 / (dt * scale)
+    out["extrapolated"] = True
+    out["sample"] = (f"FP64 oracle, FISTA with a constant step, median of iterations 2..{K} on a "
+                     f"{ns:,}-node instance of the same power-law generator (c={c}, mean degree "
+                     f"20, exponent 2.1, {wl.nnz:,} nnz): {dt:.3f} s/iteration, scaled by the "
+                     f"nonzero count (x{scale:.1f}) to the full instance; {threads} OpenMP threads")
+    out["sample_s_per_iteration"] = dt
+    del wl, rp, ci, v, U0, res
+
+    # the two smaller configurations, measured
+    wl = W.config_small_fp64(seed=0)
+    rp, ci, v, U0 = wl.numpy()
+    spec, _ = oracle.spectral_norm(rp, ci, v, True)
+    tau = 1.0 / oracle.lipschitz_bound(spec, wl.n)
+    res = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=200, step=tau, timed=True)
+    dt = _median_iteration(res)
+    out["fp64_n2000_c8"] = {"iterations": int(res.iters), "median_s_per_iteration": dt,
+                            "iters_per_s": 1.0 / dt}
+    log(f"cpu baseline: n=2,000 c=8, 200 iterations, median {dt * 1e3:.3f} ms/iteration")
+    K2 = max(3, args.cpu_medium_iters)
+    wl = W.config_medium(seed=0)
+    rp, ci, v, U0 = wl.numpy()
+    spec, _ = oracle.spectral_norm(rp, ci, v, True, max_iter=200, rtol=1e-6)
+    L0 = oracle.lipschitz_bound(spec, wl.n) / 100.0
+    res = oracle.solve(rp, ci, v, True, U0, accelerate=True, max_iter=K2, backtrack=True, L0=L0,
+                       timed=True)
+    dt = _median_iteration(res)
+    out["fp32_config_n1e6_c32_backtracking"] = {
+        "iterations": int(res.iters), "trials": int(res.trials[1:].sum()),
+        "median_s_per_iteration": dt, "iters_per_s": 1.0 / dt,
+        "note": "the oracle computes in FP64 on the FP32 values"}
+    log(f"cpu baseline: n=1e6 c=32 backtracking, {K2} iterations, median {dt:.3f} s/iteration")
+    del wl, rp, ci, v, U0, res
+    return out
 
 
 SERVE_SOLVE = dict(backtrack=True, tol_pgrad=1e-4, max_iter=300, norm_estimate="frobenius",
@@ -185,6 +321,15 @@ def serve_bench(args) -> dict:
                 if fc.Server.clock() - t_start > args.serve_timeout:
                     raise RuntimeError("serving did not finish in time")
         lat = np.asarray([done[i].t_finish - (t_start + arrivals[i]) for i in range(R)])
+        phase = {
+            "submit_delay": [done[i].t_submit - (t_start + arrivals[i]) for i in range(R)],
+            "queue": [done[i].t_setup - done[i].t_submit for i in range(R)],
+            "setup": [done[i].t_admit - done[i].t_setup for i in range(R)],
+            "start_wait": [done[i].t_start - done[i].t_admit for i in range(R)],
+            "run_to_poll": [done[i].t_finish - done[i].t_start for i in range(R)],
+        }
+        phases = {k: {"mean_ms": 1e3 * float(np.mean(v)), "p50_ms": 1e3 * percentile(v, 50),
+                      "p99_ms": 1e3 * percentile(v, 99)} for k, v in phase.items()}
         makespan = max(done[i].t_finish for i in range(R)) - (t_start + arrivals[0])
         span_seq = float(fin[-1] - arrivals[0])
         ent = {
@@ -194,6 +339,7 @@ def serve_bench(args) -> dict:
             "sequential_fp32": {"solves_per_s": R / span_seq,
                                 "p50_ms": 1e3 * percentile(lat_seq, 50),
                                 "p99_ms": 1e3 * percentile(lat_seq, 99)},
+            "served_latency_by_phase": phases,
             "results_identical_to_sequential": sum(1 for i in range(R) if done[i].f == f_seq[i]),
             "mean_iterations": float(np.mean([done[i].iter for i in range(R)])),
             "failed": sum(1 for r in done.values() if r.status != 0),
@@ -203,6 +349,8 @@ def serve_bench(args) -> dict:
             f"{ent['served']['p50_ms']:.1f} ms, p99 {ent['served']['p99_ms']:.1f} ms) vs "
             f"sequential {ent['sequential_fp32']['solves_per_s']:.1f} solves/s (p50 "
             f"{ent['sequential_fp32']['p50_ms']:.1f} ms, p99 {ent['sequential_fp32']['p99_ms']:.1f} ms)")
+        log("serving phases (mean/p50/p99 ms): " + ", ".join(
+            f"{k} {v['mean_ms']:.2f}/{v['p50_ms']:.2f}/{v['p99_ms']:.2f}" for k, v in phases.items()))
     return out
 
 
@@ -383,9 +531,14 @@ def main() -> int:
                     help="K of the mixed-precision time-to-target measurement (0 disables it)")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-gather-ceiling", action="store_true",
+                    help="skip the flat-gather measurement of the product's column sequence")
     ap.add_argument("--cpu-sample-n", type=int, default=1_000_000)
-    ap.add_argument("--cpu-iters", type=int, default=2)
-    ap.add_argument("--serve-requests", type=int, default=256,
+    ap.add_argument("--cpu-iters", type=int, default=8,
+                    help="oracle iterations on the power-law sample (median of 2..K)")
+    ap.add_argument("--cpu-medium-iters", type=int, default=12,
+                    help="oracle iterations on the n = 1e6 configuration (median of 2..K)")
+    ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests of the serving measurement (0 disables it)")
     ap.add_argument("--serve-only", action="store_true",
                     help="run only the serving measurement and print its JSON line")
@@ -490,6 +643,11 @@ def main() -> int:
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": kernels[dom]["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic}
 
+    ceiling = None
+    if not args.no_gather_ceiling and prec == "fp32":
+        ceiling = gather_ceiling(args, wl, c)
+        roofline["gather_ceiling_ms"] = ceiling["relabelled_fp32_ms"]
+        roofline["frac_of_gather_ceiling"] = ceiling["relabelled_fp32_ms"] / avg["spmm"]
     del wl
     torch.cuda.empty_cache()
     serving = None
@@ -507,7 +665,7 @@ def main() -> int:
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args, c, n, nnz)
-        log(f"cpu baseline {cpu['value']:.3e} iters/s on {cpu['cores']} threads")
+        log(f"cpu baseline {cpu['value']:.3e} iters/s (extrapolated) on {cpu['cores']} threads")
 
     value = args.steps / elapsed
     out = {
@@ -538,6 +696,7 @@ def main() -> int:
         "kernels": kernels,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "gather_ceiling": ceiling,
         "serving": serving,
         "mixed_time_to_target": mixed_target,
         "artificial_two_cluster": artificial,

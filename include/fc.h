@@ -51,7 +51,8 @@ typedef enum {
     FC_ERR_DEVICE = 4,        /* a HIP runtime call failed */
     FC_ERR_NONFINITE = 5,     /* the objective or an iterate became NaN/Inf */
     FC_ERR_STEP = 6,          /* backtracking could not find an acceptable L */
-    FC_ERR_NOT_SYMMETRIC = 7  /* validation found S != S^T or a bad CSR */
+    FC_ERR_NOT_SYMMETRIC = 7, /* validation found S != S^T or a bad CSR */
+    FC_ERR_CANCELLED = 8      /* a served request stopped by fc_server_cancel */
 } fc_status;
 
 typedef enum { FC_F64 = 0, FC_F32 = 1, FC_F16 = 2, FC_BF16 = 3 } fc_dtype;
@@ -300,6 +301,21 @@ fc_status fc_spectral_norm(const fc_csr *S, fc_diag diag, int32_t max_iter,
 fc_status fc_gram_noalloc(const void *U, fc_dtype dtype, int64_t n, int32_t c, int64_t ld,
                           void *stream, double *G_out);
 
+/* Measurement of the memory system on the sparse product's access pattern
+ * (not a step of the method; used to state the product's practical ceiling).
+ * For every e in [0, nnz), in order, gathers row col_idx[e] of U (device,
+ * `rows` rows of row_bytes = 32, 64, 128 or 256 bytes each, e.g. 32 FP32 or
+ * 64 bfloat16 clusters per row, 16-byte aligned) with the product's 16-byte
+ * lane loads and folds the bits into a checksum; no values, products or
+ * output rows.  Every col_idx[e] must lie in [0, rows) (not checked on the
+ * device).  A persistent grid of wg_per_cu (1..64) workgroups per compute
+ * unit; one untimed launch, then `reps` timed launches on `stream`;
+ * *ms_out (host) receives the mean device time per launch.  Synchronises
+ * the stream.  Errors: FC_ERR_INVALID_ARG, FC_ERR_DEVICE. */
+fc_status fc_gather_probe(const int32_t *col_idx, int64_t nnz, const void *U, int64_t rows,
+                          int32_t row_bytes, int32_t wg_per_cu, int32_t reps, void *stream,
+                          double *ms_out);
+
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *fc_last_error(void);
 
@@ -312,9 +328,11 @@ const char *fc_last_error(void);
  * admitted requests stays within hbm_budget and fewer than max_active are
  * running; it sets each one up on its own stream, then advances all running
  * requests together, one trial per tick, with batched kernels grouped by
- * padded c and step rule.  A request gets exactly the arithmetic of fc_create
- * + fc_solve with the same options, so its result does not depend on what
- * it is batched with.  Finished requests wait in the server (holding their
+ * padded c and step rule.  A newly admitted request runs its first trials
+ * on its own at once, beside the batch in flight, and joins the batched
+ * kernels at the next state poll.  A request gets exactly the arithmetic of
+ * fc_create + fc_solve with the same options, so its result does not depend
+ * on what it is batched with or when it joins.  Finished requests wait in the server (holding their
  * memory) until fc_server_release.
  * ------------------------------------------------------------------------ */
 typedef struct fc_server fc_server;
@@ -348,7 +366,10 @@ typedef struct {
     int32_t trials;
     int32_t stop_reason;    /* fc_stop_reason */
     double f;               /* final loss */
-    double t_submit, t_admit, t_finish;  /* seconds on fc_server_clock() */
+    /* seconds on fc_server_clock(): submission; set-up finished (admitted);
+       result seen by the worker's state poll; set-up started (the request
+       left the queue); first trial launched */
+    double t_submit, t_admit, t_finish, t_setup, t_start;
 } fc_result;
 
 void fc_server_opts_default(fc_server_opts *opts);
@@ -379,6 +400,15 @@ fc_status fc_server_poll(fc_server *sv, fc_result *out, int32_t max, int32_t tim
  * until the copy is done.  fc_server_release frees the request's memory. */
 fc_status fc_server_get_u(fc_server *sv, uint64_t req_id, void *U_out, fc_dtype dtype);
 fc_status fc_server_release(fc_server *sv, uint64_t req_id);
+
+/* Stop a request that is queued or running.  Asynchronous: the worker
+ * removes it at its next state poll and reports it through fc_server_poll
+ * with status FC_ERR_CANCELLED; a request that had started keeps its last
+ * accepted iterate (fc_server_get_u) and its iteration count and loss, one
+ * still queued has none.  A request that has already finished is left as it
+ * is (FC_OK).  Errors: FC_ERR_INVALID_ARG for an id that is neither queued,
+ * running nor finished and unreleased. */
+fc_status fc_server_cancel(fc_server *sv, uint64_t req_id);
 
 /* Queue lengths and the device memory held by admitted requests. */
 fc_status fc_server_stats(fc_server *sv, int32_t *n_pending, int32_t *n_active,

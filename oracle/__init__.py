@@ -94,6 +94,8 @@ def _load():
                                     ctypes.POINTER(_Opts), P, P, P, P, P,
                                     ctypes.POINTER(i32)]
         lib.fcref_solve.restype = ctypes.c_int
+        lib.fcref_solve_timed.argtypes = lib.fcref_solve.argtypes + [P]
+        lib.fcref_solve_timed.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -287,13 +289,16 @@ class SolveResult:
     trials: np.ndarray     # backtracking trials per iteration
     r: np.ndarray          # gradient-mapping norms ||Y_n - Xbar_n|| / tau_n
     stop_reason: int
+    seconds: np.ndarray | None = None   # wall time of iterations 1..iters (timed=True)
 
 
 def solve(row_ptr, col_idx, val, diag_unit: bool, X0, *, accelerate: bool = True,
           max_iter: int = 100, step: float | None = None, step_schedule=None,
           backtrack: bool = False, L0: float = 1.0, eta: float = 2.0,
-          tol_loss: float = math.nan, tol_pgrad: float = 0.0) -> SolveResult:
-    """Parallel FISTA (Alg. 4) or parallel GPA (Alg. 2/3, accelerate=False)."""
+          tol_loss: float = math.nan, tol_pgrad: float = 0.0,
+          timed: bool = False) -> SolveResult:
+    """Parallel FISTA (Alg. 4) or parallel GPA (Alg. 2/3, accelerate=False).
+    timed=True also records each iteration's wall time (seconds[1..iters])."""
     n, rp, ci, v = _csr(row_ptr, col_idx, val)
     X0 = _mat(X0, n)
     C = X0.shape[1]
@@ -315,8 +320,14 @@ def solve(row_ptr, col_idx, val, diag_unit: bool, X0, *, accelerate: bool = True
     trials = np.zeros(max_iter + 1, dtype=np.int32)
     r = np.full(max_iter + 1, np.nan)
     reason = ctypes.c_int32(0)
-    it = _load().fcref_solve(n, _ptr(rp), _ptr(ci), _ptr(v), int(diag_unit), C,
-                             _ptr(X0), ctypes.byref(opts), _ptr(X), _ptr(f), _ptr(tau),
-                             _ptr(trials), _ptr(r), ctypes.byref(reason))
+    args = (n, _ptr(rp), _ptr(ci), _ptr(v), int(diag_unit), C, _ptr(X0), ctypes.byref(opts),
+            _ptr(X), _ptr(f), _ptr(tau), _ptr(trials), _ptr(r), ctypes.byref(reason))
+    secs = None
+    if timed:
+        secs = np.full(max_iter + 1, np.nan)
+        it = _load().fcref_solve_timed(*args, _ptr(secs))
+        secs = secs[: it + 1]
+    else:
+        it = _load().fcref_solve(*args)
     return SolveResult(X, int(it), f[: it + 1], tau[: it + 1], trials[: it + 1],
-                       r[: it + 1], int(reason.value))
+                       r[: it + 1], int(reason.value), secs)

@@ -26,10 +26,12 @@
  * fixed blocks of consecutive columns added in block order), so every result
  * is the same for any number of OpenMP threads.
  */
+#define _POSIX_C_SOURCE 199309L
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
 #ifdef _OPENMP
 #include <omp.h>
 #endif
@@ -400,11 +402,36 @@ enum { FCREF_STOP_MAXITER = 0, FCREF_STOP_LOSS = 1, FCREF_STOP_PGRAD = 2,
  * backtracking rule is not in the paper either: it is checked by its
  * acceptance test and the minimality of the accepted L.
  */
+int fcref_solve_timed(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                      const double *val, int diag_unit, int C, const double *X0,
+                      const fcref_opts *opt, double *X_out, double *f_log,
+                      double *tau_log, int32_t *trials_log, double *r_log,
+                      int32_t *stop_reason, double *seconds_log);
+
 int fcref_solve(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
                 const double *val, int diag_unit, int C, const double *X0,
                 const fcref_opts *opt, double *X_out, double *f_log,
                 double *tau_log, int32_t *trials_log, double *r_log,
                 int32_t *stop_reason)
+{
+    return fcref_solve_timed(n, row_ptr, col_idx, val, diag_unit, C, X0, opt, X_out, f_log,
+                             tau_log, trials_log, r_log, stop_reason, NULL);
+}
+
+static double wall_seconds(void)
+{
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* fcref_solve, also recording the wall time of every iteration in
+ * seconds_log[1..it] (may be NULL); the arithmetic is the same. */
+int fcref_solve_timed(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                      const double *val, int diag_unit, int C, const double *X0,
+                      const fcref_opts *opt, double *X_out, double *f_log,
+                      double *tau_log, int32_t *trials_log, double *r_log,
+                      int32_t *stop_reason, double *seconds_log)
 {
     const size_t nc = (size_t)n * (size_t)C;
     double *Xbar = (double *)malloc(sizeof(double) * nc);      /* Xbar_n     */
@@ -435,6 +462,7 @@ int fcref_solve(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
     int completed = 0, failed = 0;
     int32_t reason = FCREF_STOP_MAXITER;
     for (int it = 1; it <= opt->max_iter; ++it) {
+        const double t_start = wall_seconds();
         /* projected gradient step at Y_n */
         fcref_x_s(n, row_ptr, col_idx, val, diag_unit, C, Y, YS);
         fcref_share(n, C, Y, share);
@@ -525,6 +553,8 @@ int fcref_solve(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
         for (int64_t e = 0; e < (int64_t)nc; ++e)
             Y[e] = Xbar[e] + beta * (Xbar[e] - Xprev[e]);
         t = t_next;
+        if (seconds_log)
+            seconds_log[it] = wall_seconds() - t_start;
     }
 
     if (stop_reason)

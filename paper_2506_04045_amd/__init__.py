@@ -19,7 +19,7 @@ import torch
 
 from . import _native as N
 
-__all__ = ["Solver", "Server", "Info", "objective", "project", "spmm", "gram", "gram_noalloc", "spectral_norm",
+__all__ = ["Solver", "Server", "Info", "objective", "project", "spmm", "gram", "gram_noalloc", "gather_probe", "spectral_norm",
            "library_path"]
 
 _PREC = {"fp64": N.FC_PREC_FP64, "fp32": N.FC_PREC_FP32, "mixed": N.FC_PREC_MIXED}
@@ -235,6 +235,8 @@ class Result:
     t_submit: float
     t_admit: float
     t_finish: float
+    t_setup: float
+    t_start: float
 
 
 def _server_options(max_active, hbm_budget, ticks_per_poll, use_graph, grid_fused=None,
@@ -337,7 +339,12 @@ class Server:
         N.check(N.load().fc_server_poll(self._h, buf, max_results, int(timeout_us),
                                         ctypes.byref(cnt)))
         return [Result(r.req_id, r.status, r.iter, r.trials, r.stop_reason, r.f, r.t_submit,
-                       r.t_admit, r.t_finish) for r in buf[: cnt.value]]
+                       r.t_admit, r.t_finish, r.t_setup, r.t_start) for r in buf[: cnt.value]]
+
+    def cancel(self, req_id: int) -> None:
+        """Stop a queued or running request (fc_server_cancel); it is reported
+        by poll with status FC_ERR_CANCELLED."""
+        N.check(N.load().fc_server_cancel(self._h, int(req_id)))
 
     def get_u(self, req_id: int, dtype=torch.float32) -> torch.Tensor:
         _, _, n, c = self._keep[int(req_id)]
@@ -439,6 +446,22 @@ def gram_noalloc(U: torch.Tensor, G_out: torch.Tensor, stream=None) -> torch.Ten
     N.check(N.load().fc_gram_noalloc(U.data_ptr(), _DT[U.dtype], n, c, U.stride(0),
                                      _stream_ptr(stream), G_out.data_ptr()))
     return G_out
+
+
+def gather_probe(col_idx: torch.Tensor, U: torch.Tensor, wg_per_cu: int = 16, reps: int = 5,
+                 stream=None) -> float:
+    """Mean device milliseconds of one flat pass that gathers row col_idx[e]
+    of U for every e (fc_gather_probe; a memory-system measurement)."""
+    col_idx = _dev(col_idx, "col_idx", (torch.int32,))
+    U = _dev(U, "U")
+    row_bytes = U.shape[1] * U.element_size()
+    if U.dim() != 2 or row_bytes not in (32, 64, 128, 256):
+        raise ValueError("U must be 2-D with rows of 32, 64, 128 or 256 bytes")
+    ms = ctypes.c_double(0.0)
+    N.check(N.load().fc_gather_probe(col_idx.data_ptr(), col_idx.numel(), U.data_ptr(),
+                                     U.shape[0], row_bytes, wg_per_cu, reps,
+                                     _stream_ptr(stream), ctypes.byref(ms)))
+    return float(ms.value)
 
 
 def spectral_norm(row_ptr, col_idx, val, diag: str = "unit", max_iter: int = 1000,

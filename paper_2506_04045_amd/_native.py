@@ -23,7 +23,8 @@ FC_STOP_NONE, FC_STOP_MAXITER, FC_STOP_LOSS, FC_STOP_PGRAD, FC_STOP_ERROR = 0, 1
 
 STATUS_NAMES = {0: "FC_OK", 1: "FC_ERR_INVALID_ARG", 2: "FC_ERR_UNSUPPORTED",
                 3: "FC_ERR_OUT_OF_MEMORY", 4: "FC_ERR_DEVICE", 5: "FC_ERR_NONFINITE",
-                6: "FC_ERR_STEP", 7: "FC_ERR_NOT_SYMMETRIC"}
+                6: "FC_ERR_STEP", 7: "FC_ERR_NOT_SYMMETRIC", 8: "FC_ERR_CANCELLED"}
+STATUS_CODES = {name: code for code, name in STATUS_NAMES.items()}
 
 EXPORTED = [
     "fc_options_default", "fc_create", "fc_step", "fc_step_profiled", "fc_solve", "fc_get_u", "fc_get_history",
@@ -32,7 +33,7 @@ EXPORTED = [
     "fc_server_opts_default", "fc_server_clock", "fc_server_create", "fc_server_submit",
     "fc_server_poll", "fc_server_get_u", "fc_server_release", "fc_server_stats",
     "fc_server_destroy", "fc_server_tune", "fc_hessian_vector", "fc_curvature",
-    "fc_gram_noalloc",
+    "fc_gram_noalloc", "fc_gather_probe", "fc_server_cancel",
 ]
 
 
@@ -81,7 +82,8 @@ class Result(ctypes.Structure):
                 ("iter", ctypes.c_int32), ("trials", ctypes.c_int32),
                 ("stop_reason", ctypes.c_int32), ("f", ctypes.c_double),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
-                ("t_finish", ctypes.c_double)]
+                ("t_finish", ctypes.c_double), ("t_setup", ctypes.c_double),
+                ("t_start", ctypes.c_double)]
 
 
 _lib = None
@@ -131,6 +133,8 @@ def load() -> ctypes.CDLL:
     lib.fc_gram.restype = st
     lib.fc_gram_noalloc.argtypes = [P, ctypes.c_int, i64, i32, i64, P, P]
     lib.fc_gram_noalloc.restype = st
+    lib.fc_gather_probe.argtypes = [P, i64, P, i64, i32, i32, i32, P, ctypes.POINTER(f64)]
+    lib.fc_gather_probe.restype = st
     lib.fc_spectral_norm.argtypes = [ctypes.POINTER(CSR), ctypes.c_int, i32, f64, P,
                                      ctypes.POINTER(f64), ctypes.POINTER(i32)]
     lib.fc_spectral_norm.restype = st
@@ -151,6 +155,8 @@ def load() -> ctypes.CDLL:
     lib.fc_server_get_u.restype = st
     lib.fc_server_release.argtypes = [P, ctypes.c_uint64]
     lib.fc_server_release.restype = st
+    lib.fc_server_cancel.argtypes = [P, ctypes.c_uint64]
+    lib.fc_server_cancel.restype = st
     lib.fc_server_tune.argtypes = [ctypes.POINTER(ServerOpts), i32, ctypes.POINTER(CSR),
                                    ctypes.POINTER(Options), ctypes.POINTER(P), ctypes.c_int, P,
                                    ctypes.POINTER(ServerOpts), ctypes.POINTER(f64),

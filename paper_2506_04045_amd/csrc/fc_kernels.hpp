@@ -1907,4 +1907,54 @@ __global__ __launch_bounds__(256) void k_project(const T *__restrict__ V, T *__r
     }
 }
 
+// ---------------------------------------------------------------------------
+// Memory-system probe (a measurement, not a step of the method): gathers, for
+// every stored nonzero e in order, the row col[e] of U with the sparse
+// product's 16-byte lane loads, and nothing else -- no values, no
+// multiplications, no output rows.  A flat, perfectly balanced loop over the
+// nonzeros: each team of GS lanes (one 16-byte piece of a row per lane)
+// keeps DEPTH gathers in flight and loads the next column indices while they
+// are outstanding.  Its time on the product's own column sequence is the
+// floor the product's gathers can reach on this memory system.
+// ---------------------------------------------------------------------------
+template <int GS, int DEPTH>
+__global__ __launch_bounds__(256) void k_gather_probe(const int32_t *__restrict__ col, int64_t nnz,
+                                                      const uint4 *__restrict__ U, int64_t row_pieces,
+                                                      double *__restrict__ checksum) {
+    constexpr int TEAMS = 256 / GS;
+    const int team = threadIdx.x / GS, sub = threadIdx.x % GS;
+    const int64_t nteam = (int64_t)gridDim.x * TEAMS;
+    const int64_t t0 = (int64_t)blockIdx.x * TEAMS + team;
+    uint32_t acc = 0;
+    int32_t jn[DEPTH];
+#pragma unroll
+    for (int u = 0; u < DEPTH; ++u) {
+        const int64_t e = t0 + u * nteam;
+        jn[u] = e < nnz ? col[e] : -1;
+    }
+    for (int64_t e0 = t0; e0 < nnz; e0 += DEPTH * nteam) {
+        uint4 g[DEPTH];
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u)
+            g[u] = jn[u] >= 0 ? U[(int64_t)jn[u] * row_pieces + sub] : uint4{0, 0, 0, 0};
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u) {
+            const int64_t e = e0 + DEPTH * nteam + u * nteam;
+            jn[u] = e < nnz ? col[e] : -1;
+        }
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u)
+            acc += g[u].x ^ g[u].y ^ g[u].z ^ g[u].w;
+    }
+    __shared__ uint32_t sh[256];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t x = 0;
+        for (int k = 0; k < 256; ++k)
+            x ^= sh[k];
+        atomicAdd(checksum, (double)(x & 0xffff));
+    }
+}
+
 }  // namespace fc

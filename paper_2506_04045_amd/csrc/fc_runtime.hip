@@ -23,6 +23,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <set>
 #include <mutex>
 #include <string>
 #include <thread>
@@ -1701,6 +1702,52 @@ fc_status fc_project(const void *V, void *out, fc_dtype dtype, int64_t rows, int
     }
 #undef PROJ
     HIPCHK(hipGetLastError());
+    return FC_OK;
+}
+
+fc_status fc_gather_probe(const int32_t *col_idx, int64_t nnz, const void *U, int64_t rows,
+                          int32_t row_bytes, int32_t wg_per_cu, int32_t reps, void *stream,
+                          double *ms_out) {
+    g_last_error.clear();
+    if (!col_idx || !U || !ms_out || nnz < 1 || rows < 1 || reps < 1)
+        return fail(FC_ERR_INVALID_ARG, "need col_idx, U, ms_out, nnz >= 1, rows >= 1, reps >= 1");
+    if (row_bytes != 32 && row_bytes != 64 && row_bytes != 128 && row_bytes != 256)
+        return fail(FC_ERR_INVALID_ARG, "row_bytes must be 32, 64, 128 or 256");
+    if (wg_per_cu < 1 || wg_per_cu > 64)
+        return fail(FC_ERR_INVALID_ARG, "wg_per_cu must be in [1, 64]");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t pieces = row_bytes / 16;
+    const int teams = 256 / (int)pieces;
+    const int g = grid_1d(cdiv(nnz, teams), 1, (int64_t)device_cus() * wg_per_cu);
+    DevBuf sum;
+    HIPCHK(dev_alloc(sum, sizeof(double), s));
+    HIPCHK(hipMemsetAsync(sum.p, 0, sizeof(double), s));
+    auto launch = [&]() {
+        const uint4 *u = (const uint4 *)U;
+        double *cs = (double *)sum.p;
+        switch (pieces) {
+        case 2: hipLaunchKernelGGL((k_gather_probe<2, 4>), dim3(g), dim3(256), 0, s, col_idx, nnz, u, pieces, cs); break;
+        case 4: hipLaunchKernelGGL((k_gather_probe<4, 4>), dim3(g), dim3(256), 0, s, col_idx, nnz, u, pieces, cs); break;
+        case 8: hipLaunchKernelGGL((k_gather_probe<8, 4>), dim3(g), dim3(256), 0, s, col_idx, nnz, u, pieces, cs); break;
+        default: hipLaunchKernelGGL((k_gather_probe<16, 4>), dim3(g), dim3(256), 0, s, col_idx, nnz, u, pieces, cs); break;
+        }
+    };
+    launch();   // warm-up
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+    for (int r = 0; r < reps; ++r)
+        launch();
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    hipError_t e = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    HIPCHK(e);
+    HIPCHK(hipGetLastError());
+    *ms_out = (double)ms / reps;
     return FC_OK;
 }
 

@@ -90,7 +90,7 @@ def test_staggered_arrivals_join_running_batches(fc):
     for i in range(len(reqs)):
         r, U = served[i]
         assert r.status == 0 and r.f == alone[i][0].f and np.array_equal(U, alone[i][1])
-        assert r.t_submit <= r.t_admit <= r.t_finish
+        assert r.t_submit <= r.t_setup <= r.t_admit <= r.t_start <= r.t_finish
 
 
 def test_admission_respects_the_memory_budget(fc):
@@ -206,3 +206,56 @@ def test_large_request_sums_as_it_does_alone(fc):
         assert r.status == 0 and r.iter == info.iter
         assert r.f == info.f, (i, r.f, info.f)
         assert np.array_equal(U, U_ref), i
+
+
+def test_cancel_queued_and_running_requests(fc):
+    """fc_server_cancel: a running request stops with its last accepted
+    iterate (rows on the simplex, fewer iterations than its budget), a queued
+    one leaves the queue without running, the others finish exactly as they
+    do alone, and unknown ids are rejected."""
+    from paper_2506_04045_amd import _native as N
+    cancelled = N.STATUS_CODES["FC_ERR_CANCELLED"]
+    big = W.er_planted(200_000, 32, 20.0, 0.05, 901).to("cuda")
+    small = _requests(3, seed0=910)
+    alone = [_alone(fc, wl) for wl in small]
+    budget = 20_000
+    long_solve = dict(SOLVE, max_iter=budget, tol_pgrad=0.0)
+    seen = {}
+
+    def collect(timeout_us=20000):
+        for r in sv.poll(16, timeout_us=timeout_us):
+            seen[r.req_id] = r
+            if r.req_id in (10, 12):
+                k = r.req_id - 10
+                assert r.status == 0 and r.f == alone[k][0].f
+                assert np.array_equal(sv.get_u(r.req_id).cpu().numpy(), alone[k][1])
+
+    with fc.Server(max_active=2, ticks_per_poll=2) as sv:
+        sv.submit(0, big.row_ptr, big.col_idx, big.val, big.c, big.U0, **long_solve)
+        sv.submit(1, big.row_ptr, big.col_idx, big.val, big.c, big.U0, **long_solve)
+        for i, wl in enumerate(small):       # queued behind the two big ones
+            sv.submit(10 + i, wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, **SOLVE)
+        time.sleep(0.3)
+        sv.cancel(0)                         # running
+        sv.cancel(11)                        # queued (both slots are taken)
+        with pytest.raises(N.FcError):
+            sv.cancel(12345)
+        t0 = time.time()
+        while 0 not in seen or 11 not in seen:
+            collect()
+            assert time.time() - t0 < 60
+        r0, r11 = seen[0], seen[11]
+        assert r0.status == cancelled and 0 < r0.iter < budget
+        U0c = sv.get_u(0).double()
+        assert (U0c >= 0).all() and float((U0c.sum(1) - 1).abs().max()) <= 1e-5
+        assert r11.status == cancelled and r11.iter == 0
+        sv.cancel(1)
+        sv.release(0)
+        sv.release(11)
+        t0 = time.time()
+        while len(seen) < 5:
+            collect()
+            assert time.time() - t0 < 60
+        assert seen[1].status == cancelled and seen[1].iter < budget
+        sv.cancel(10)                        # already finished: left as it is
+        assert sv.poll(16, timeout_us=0) == []
