@@ -281,7 +281,8 @@ def serve_bench(args) -> dict:
         tuned = fc.tune_server([dict(row_ptr=w.row_ptr, col_idx=w.col_idx, val=w.val, c=w.c,
                                      U0=w.U0, **SERVE_SOLVE) for w in sample],
                                max_active=args.serve_slots, hbm_budget=args.serve_budget_gb * 2**30,
-                               ticks_per_poll=args.serve_ticks, use_graph=bool(args.serve_graph))
+                               ticks_per_poll=args.serve_ticks, use_graph=bool(args.serve_graph),
+                               solo_max=args.serve_solo)
         sched = {k: tuned[k] for k in ("ticks_per_poll", "use_graph", "grid_fused", "grid_spmm")}
         tuning = {"sample_requests": args.serve_tune, "server_runs": tuned["runs"],
                   "seconds": time.perf_counter() - t0,
@@ -289,7 +290,8 @@ def serve_bench(args) -> dict:
         del sample
         log(f"serving: tuned schedule {sched} ({tuned['runs']} runs, "
             f"{tuning['seconds']:.1f} s, sample at {tuned['solves_per_s']:.1f} solves/s)")
-    out = {"requests": R, "slots": args.serve_slots, "ticks_per_poll": sched["ticks_per_poll"],
+    out = {"requests": R, "slots": args.serve_slots, "solo_max": args.serve_solo,
+           "ticks_per_poll": sched["ticks_per_poll"],
            "graph": bool(sched["use_graph"]), "launch_table": {"grid_fused": sched["grid_fused"],
                                                              "grid_spmm": sched["grid_spmm"]},
            "autotuner": tuning,
@@ -305,7 +307,7 @@ def serve_bench(args) -> dict:
         lat_seq = np.asarray(fin) - arrivals
         done = {}
         with fc.Server(max_active=args.serve_slots, hbm_budget=args.serve_budget_gb * 2**30,
-                       **sched) as sv:
+                       solo_max=args.serve_solo, **sched) as sv:
             t_start = fc.Server.clock()
             k = 0
             while len(done) < R:
@@ -545,6 +547,9 @@ def main() -> int:
     ap.add_argument("--serve-load", default="2.0,0.5",
                     help="arrival rates as multiples of the sequential solve rate (comma list)")
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-solo", type=int, default=4,
+                    help="active requests up to which a new request runs unbatched on its own "
+                         "stream (fc_server_opts.solo_max; 0 batches every request)")
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-ticks", type=int, default=16,
                     help="batched iterations the serving worker launches between state polls")

@@ -357,6 +357,14 @@ typedef struct {
        fc_server_tune measures them. */
     int32_t grid_fused[5];
     int32_t grid_spmm[5];
+    /* Solo lane: while at most solo_max requests are active (0..8; default
+       4, the hardware queues the GPU gives one process), a newly admitted
+       request runs unbatched on a stream of its own, in chunks of
+       ticks_per_poll trials, as fc_solve runs it; the worker checks its
+       chunks by events instead of a poll of every stream.  0 batches every
+       request. */
+    int32_t solo_max;
+    int32_t reserved;
 } fc_server_opts;
 
 typedef struct {

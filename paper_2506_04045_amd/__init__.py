@@ -240,8 +240,10 @@ class Result:
 
 
 def _server_options(max_active, hbm_budget, ticks_per_poll, use_graph, grid_fused=None,
-                    grid_spmm=None) -> N.ServerOpts:
+                    grid_spmm=None, solo_max=None) -> N.ServerOpts:
     o = N.default_server_options()
+    if solo_max is not None:
+        o.solo_max = int(solo_max)
     o.max_active = int(max_active)
     o.hbm_budget = float(hbm_budget)
     o.ticks_per_poll = int(ticks_per_poll)
@@ -256,14 +258,16 @@ def _server_options(max_active, hbm_budget, ticks_per_poll, use_graph, grid_fuse
 
 
 def tune_server(requests, max_active: int = 64, hbm_budget: float = 32.0 * 2**30,
-                ticks_per_poll: int = 16, use_graph: bool = False, stream=None) -> dict:
+                ticks_per_poll: int = 16, use_graph: bool = False, stream=None,
+                solo_max: int | None = None) -> dict:
     """fc_server_tune on sample requests, each a dict with row_ptr, col_idx,
     val, c, U0 (or None) and solver options as Solver takes them.  Returns
     the chosen schedule (ticks_per_poll, use_graph, grid_fused, grid_spmm:
     keyword arguments of Server), the rate of the final run and the number
     of server runs."""
     lib = N.load()
-    base = _server_options(max_active, hbm_budget, ticks_per_poll, use_graph)
+    base = _server_options(max_active, hbm_budget, ticks_per_poll, use_graph,
+                           solo_max=solo_max)
     k = len(requests)
     if k < 1:
         raise ValueError("tune_server needs at least one request")
@@ -305,13 +309,15 @@ class Server:
 
     def __init__(self, max_active: int = 64, hbm_budget: float = 32.0 * 2**30,
                  ticks_per_poll: int = 16, use_graph: bool = False, grid_fused=None,
-                 grid_spmm=None, stream=None):
+                 grid_spmm=None, stream=None, solo_max: int | None = None):
         """grid_fused / grid_spmm: the launch table, five workgroups-per-CU
         entries for padded widths 4, 8, 16, 32, 64 (0 = built-in), as
-        tune_server returns it."""
+        tune_server returns it.  solo_max: active requests up to which a new
+        request runs unbatched on a stream of its own (None = the library's
+        default, 4; 0 batches every request)."""
         lib = N.load()
         o = _server_options(max_active, hbm_budget, ticks_per_poll, use_graph, grid_fused,
-                            grid_spmm)
+                            grid_spmm, solo_max)
         h = ctypes.c_void_p()
         N.check(lib.fc_server_create(ctypes.byref(o), None if stream is None
                                      else int(stream.cuda_stream), ctypes.byref(h)))

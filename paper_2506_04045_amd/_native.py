@@ -74,7 +74,8 @@ class ServerOpts(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_active", ctypes.c_int32),
                 ("hbm_budget", ctypes.c_double), ("ticks_per_poll", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("grid_fused", ctypes.c_int32 * 5),
-                ("grid_spmm", ctypes.c_int32 * 5)]
+                ("grid_spmm", ctypes.c_int32 * 5), ("solo_max", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
