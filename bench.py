@@ -41,6 +41,20 @@ def kernel_source_sha() -> str:
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
+def single_pass_bytes(n: int, c: int, nnz: int, n_long: int, nnz_long: int) -> dict:
+    """Bytes each launch of the single-pass iteration must move at least (FP32;
+    index 4 B, value 4 B, row pointer 8 B).  The single-pass kernel reads the
+    light rows' indices and values, every row of Y_n once (the gathers and its
+    own rows), Xbar_{n-1}, the long rows' products from the pre-pass, and
+    writes Xbar_n and Y_{n+1}; the pre-pass reads the long rows' indices and
+    values and writes their products.  Together: 8(n+1) + 8 nnz + 4 (4nc) plus
+    the long rows' products written and read."""
+    row = 8 * (n + 1)
+    single = row + 8 * (nnz - nnz_long) + 4 * (4 * n * c) + 4 * n_long * c
+    prepass = 8 * (n_long + 1) + 8 * nnz_long + 4 * n_long * c
+    return {"fused": single, "spmm": prepass, "iteration_minimum": row + 8 * nnz + 16 * n * c}
+
+
 def algorithmic_bytes(n: int, c: int, nnz: int, precision: str) -> dict:
     """Bytes each launch must move at least (index 4 B, row pointer 8 B)."""
     b_val = {"fp32": 4, "fp64": 8, "mixed": 2}[precision]
@@ -525,6 +539,8 @@ def main() -> int:
                     help="Beck-Teboulle backtracking (L0 = L_thm/100) instead of the constant step")
     ap.add_argument("--defer-loss", type=int, default=1,
                     help="1: each iterate's loss is formed during the next pass (fc_options.defer_loss)")
+    ap.add_argument("--single-pass", type=int, default=0,
+                    help="1: the single-pass iteration (fc_options.single_pass; FP32, fixed step)")
     ap.add_argument("--no-smaller", action="store_true",
                     help="skip the n = 2,000 FP64 and n = 1e6 backtracking runs")
     ap.add_argument("--no-artificial", action="store_true",
@@ -608,10 +624,15 @@ def main() -> int:
 
     prec = args.precision
     t0 = time.perf_counter()
-    defer = bool(args.defer_loss) and not args.backtrack
+    single = bool(args.single_pass) and not args.backtrack and prec == "fp32"
+    defer = bool(args.defer_loss) and not args.backtrack and not single
+    deg = wl.row_ptr[1:] - wl.row_ptr[:-1]
+    long_rows = deg > 64
+    n_long, nnz_long = int(long_rows.sum()), int(deg[long_rows].sum())
+    del deg, long_rows
     solver = fc.Solver(wl.row_ptr, wl.col_idx, wl.val, args.c, wl.U0, precision=prec,
                        accelerate=True, step=0.0, backtrack=args.backtrack, reorder=args.reorder,
-                       defer_loss=defer)
+                       defer_loss=defer, single_pass=single)
     torch.cuda.synchronize()
     log(f"solver created in {time.perf_counter() - t0:.1f} s")
 
@@ -633,26 +654,39 @@ def main() -> int:
     n, c, nnz = wl.n, args.c, wl.nnz
     launches = max(1, kt["launches"])
     avg = {k: kt[f"{k}_ms"] / launches for k in ("fused", "spmm", "reduce", "control")}
-    alg = algorithmic_bytes(n, c, nnz, prec)
+    alg = (single_pass_bytes(n, c, nnz, n_long, nnz_long) if single
+           else algorithmic_bytes(n, c, nnz, prec))
     kernels = {}
     for k in ("spmm", "fused"):
         gbs = alg[k] / (avg[k] * 1e-3) / 1e9
         kernels[k] = {"avg_ms": avg[k], "algorithmic_bytes": alg[k], "achieved_GBps": gbs,
                       "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+    if single:
+        kernels["fused"]["kernel"] = "k_single (single-pass iteration, light rows' products included)"
+        kernels["spmm"]["kernel"] = f"k_spmm pre-pass over the {n_long:,} rows longer than 64 nonzeros"
     kernels["reduce"] = {"avg_ms": avg["reduce"]}
     kernels["control"] = {"avg_ms": avg["control"]}
     dom = max(("spmm", "fused"), key=lambda k: avg[k])
-    wkey = f"powerlaw_n{n}_c{c}_{prec}_{args.reorder}" + ("_deferred" if defer else "")
+    wkey = (f"powerlaw_n{n}_c{c}_{prec}_{args.reorder}" + ("_deferred" if defer else "")
+            + ("_single" if single else ""))
     traffic = measured_traffic(dom, wkey)
     roofline = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["achieved_GBps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": kernels[dom]["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic}
 
     ceiling = None
+    if single:
+        it_gbs = alg["iteration_minimum"] / (elapsed / args.steps) / 1e9
+        roofline["iteration_minimum_bytes"] = alg["iteration_minimum"]
+        roofline["iteration_GBps"] = it_gbs
+        roofline["iteration_frac"] = it_gbs / HBM_PEAK_GBS
     if not args.no_gather_ceiling and prec == "fp32":
         ceiling = gather_ceiling(args, wl, c)
         roofline["gather_ceiling_ms"] = ceiling["relabelled_fp32_ms"]
-        roofline["frac_of_gather_ceiling"] = ceiling["relabelled_fp32_ms"] / avg["spmm"]
+        # the product's gathers: all of them in the sparse product, or the
+        # single-pass kernel's and the pre-pass's together
+        gather_ms = avg["spmm"] + (avg["fused"] if single else 0.0)
+        roofline["frac_of_gather_ceiling"] = ceiling["relabelled_fp32_ms"] / gather_ms
     del wl
     torch.cuda.empty_cache()
     serving = None
@@ -693,9 +727,12 @@ def main() -> int:
                          + ("with backtracking (L0 = L_thm/100, eta 2)" if args.backtrack else
                             "constant step 1/L (Theorem 3.1)")
                          + f", {prec}, articles relabelled: {args.reorder}, "
-                         f"loss evaluation deferred: {defer}"),
+                         + (f"single-pass iteration (loss formed at the read-out after the "
+                            f"timed iterations, inside the timed region)" if single else
+                            f"loss evaluation deferred: {defer}")),
             "n": n, "c": c, "nnz": nnz, "precision": prec, "reorder": args.reorder,
-            "defer_loss": defer, "backtrack": bool(args.backtrack), "tau": tau,
+            "defer_loss": defer, "single_pass": single, "backtrack": bool(args.backtrack),
+            "tau": tau,
             "trials_per_iteration": trials_per_iter, "f0": f0, "f_end": f_end,
         },
         "kernels": kernels,

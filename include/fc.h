@@ -124,7 +124,7 @@ typedef struct {
     int32_t reorder;           /* fc_reorder: FC_REORDER_NONE (default) or
                                   FC_REORDER_DEGREE, see below */
     int32_t defer_loss;        /* 1: deferred loss evaluation, see below (default 0) */
-    int32_t reserved2;
+    int32_t single_pass;       /* 1: single-pass iteration, see below (default 0) */
 } fc_options;
 
 /* Internal numbering of the articles.  FC_REORDER_DEGREE renumbers them by
@@ -157,6 +157,23 @@ typedef enum { FC_REORDER_NONE = 0, FC_REORDER_DEGREE = 1 } fc_reorder;
  * reason as the default mode.  Iterates agree with the default mode to
  * rounding.  Checkpoints record the mode; the serving engine does not
  * accept it (FC_ERR_UNSUPPORTED). */
+
+/* Single-pass iteration (single_pass = 1; constant or scheduled steps,
+ * FC_PREC_FP64 or FC_PREC_FP32, tol_loss NaN).  Each iteration sweeps the
+ * rows once: it applies S to the stored extrapolated point Y_n (eq.
+ * gradient_column), takes the projected step (Alg. 2 step, Alg. 1) and forms
+ * the next extrapolated point Y_{n+1} of Alg. 4 in the same pass, so S is
+ * applied once per iteration and only Xbar and the two Y buffers are kept
+ * (the default mode stores S Xbar and re-forms Y from two iterates).  The
+ * structured loss of Alg. 3 needs S Xbar_n, which this mode never forms
+ * inside the iteration: it is evaluated once at the end of every fc_step /
+ * fc_solve call (one extra sparse product), so info.f is the loss of the
+ * returned iterate and info.f_prev that of the previous read-out, and the
+ * history holds losses only at read-outs (NaN elsewhere).  The gradient-
+ * mapping stop is available, the loss stop is not (FC_ERR_UNSUPPORTED).
+ * Iterates agree with the default mode to rounding.  Xbar is updated in
+ * place, so after FC_ERR_NONFINITE the handle holds the failed iterate.
+ * Checkpoints record the mode; the serving engine does not accept it. */
 
 /* Per-solver progress, returned by fc_step and fc_solve. */
 typedef struct {
@@ -193,8 +210,10 @@ fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0,
 
 /* Device time per kernel of the launches made by fc_step_profiled. */
 typedef struct {
-    double fused_ms;    /* extrapolation, gradient, step, projection and Grams */
-    double spmm_ms;     /* sparse product S Xbar of the trial point */
+    double fused_ms;    /* extrapolation, gradient, step, projection and Grams (single-
+                           pass mode: the single-pass kernel, light rows' products included) */
+    double spmm_ms;     /* sparse product S Xbar of the trial point (single-pass mode: its
+                           pre-pass over the rows longer than 64 stored nonzeros) */
     double reduce_ms;   /* the fixed-order reductions of the partial sums */
     double control_ms;  /* the one-workgroup controller */
     int32_t launches;   /* trials launched (one launch of each kernel per trial) */

@@ -92,7 +92,7 @@ def _options(c: int, precision: str = "fp32", diag: str = "unit", accelerate: bo
              max_iter: int = 100, check_every: int = 16, tol_loss: float = math.nan,
              tol_pgrad: float = 0.0, validate: bool = False,
              norm_estimate: str = "power", reorder: str = "none",
-             defer_loss: bool = False) -> N.Options:
+             defer_loss: bool = False, single_pass: bool = False) -> N.Options:
     opt = N.default_options()
     opt.c = int(c)
     opt.precision = _PREC[precision]
@@ -110,6 +110,7 @@ def _options(c: int, precision: str = "fp32", diag: str = "unit", accelerate: bo
     opt.norm_estimate = {"power": 0, "frobenius": 1}[norm_estimate]
     opt.reorder = {"none": 0, "degree": 1}[reorder]
     opt.defer_loss = int(bool(defer_loss))
+    opt.single_pass = int(bool(single_pass))
     return opt
 
 
@@ -122,14 +123,14 @@ class Solver:
                  max_iter: int = 100, check_every: int = 16, tol_loss: float = math.nan,
                  tol_pgrad: float = 0.0, validate: bool = False, step_schedule=None,
                  norm_estimate: str = "power", reorder: str = "none", defer_loss: bool = False,
-                 stream=None):
+                 single_pass: bool = False, stream=None):
         lib = N.load()
         self._csr = _CsrView(row_ptr, col_idx, val)
         self.n, self.c = self._csr.n, int(c)
         self.precision = precision
         opt = _options(c, precision, diag, accelerate, step, backtrack, L0, eta, max_iter,
                        check_every, tol_loss, tol_pgrad, validate, norm_estimate, reorder,
-                       defer_loss)
+                       defer_loss, single_pass)
         self._sched = None
         if step_schedule is not None:
             self._sched = np.ascontiguousarray(step_schedule, dtype=np.float64)

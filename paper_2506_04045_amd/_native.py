@@ -53,7 +53,7 @@ class Options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("norm_estimate", ctypes.c_int32),
                 ("step_schedule", ctypes.POINTER(ctypes.c_double)),
                 ("step_schedule_len", ctypes.c_int32), ("reorder", ctypes.c_int32),
-                ("defer_loss", ctypes.c_int32), ("reserved2", ctypes.c_int32)]
+                ("defer_loss", ctypes.c_int32), ("single_pass", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):

@@ -162,12 +162,18 @@ struct Inst {
     double *red_mats;
     int32_t g_fused, g_spmm, g_comb, g_red;
     int32_t defer;   // 1: products hold S_off X (no unit diagonal, no trace terms)
-    int32_t pad0;
+    int32_t pass_kind; // PASS_*: how the sparse product and controller treat the instance
     int64_t nt_from; // FP32 products gather rows >= nt_from non-temporally (0: none)
     const double *sched;
     double *hist_f, *hist_tau, *hist_r;
     int32_t *hist_trials;
 };
+
+// Inst::pass_kind.  PASS_SINGLE: the single-pass iteration (k_single), whose
+// controller sees no loss per iteration; PASS_LONG: the copy of a single-pass
+// instance that its sparse product pre-pass runs with -- medium and heavy
+// rows only, light rows left to k_single.
+enum { PASS_DEFAULT = 0, PASS_SINGLE = 1, PASS_LONG = 2 };
 
 // One entry of a batch table: block `blk` of instance `inst`.
 struct VBlk {
@@ -726,7 +732,7 @@ __device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, 
     const int tid = threadIdx.x;
     double trace_acc = 0.0;
 
-    {   // light rows
+    if (I.pass_kind != PASS_LONG) {   // light rows
         const int team = tid / Lc::TEAM, lt = tid % Lc::TEAM;
         const int slot = lt / Lc::GS, sub = lt % Lc::GS;
         const int64_t nblocks = (n + Lc::TEAMS - 1) / Lc::TEAMS;
@@ -1439,6 +1445,286 @@ __global__ __launch_bounds__(256, (sizeof(T) == 4 ? 2 : 1)) void k_fused_b(const
     }
 }
 
+// ---------------------------------------------------------------------------
+// Single-pass iteration (constant or scheduled steps): one sweep over the
+// rows per iteration that takes the step from the stored extrapolated point
+// Y_n instead of re-forming it from two iterates and their products.
+//
+// A 64-row tile at a time, a workgroup
+//   A. sums the tile's rows of S_eff Y_n -- rows of at most light_max stored
+//      nonzeros by teams of lanes that gather rows of Y_n (the sparse
+//      product's loop), longer rows from the pre-pass, which left their
+//      products S_off Y_n in Z -- into LDS;
+//   B. with the fused kernel's lane layout reads y_i and xbar_{n-1,i}, adds
+//      the unit diagonal, forms grad = -4 (S_eff y - y (G_Y - mu 1 1^T)) (Y G
+//      on the matrix cores), v = y - tau grad and its projection p onto the
+//      simplex (Xbar_n), and the next extrapolated point
+//      y' = (1 + beta') p - beta' xbar_{n-1};
+//   C. stages p and y' in LDS, writes p over xbar_{n-1} (each row is read
+//      and written by its own tile only) and y' into the other Y buffer, and
+//      accumulates the Gram matrix of y' on the matrix cores.
+// The partials hold that Gram matrix (the fused layout's second matrix) and
+// the scalars ||Y_n - Xbar_n||^2 and the count of non-finite step values.
+// S is applied once per iteration, to Y_n, and nothing of size n x c is
+// stored besides Xbar and Y; the loss needs S Xbar and is formed only when
+// the iterate is read out.
+// ---------------------------------------------------------------------------
+template <typename T, int CP, bool ACCEL>
+__device__ __forceinline__ void single_body(const Inst &I, int64_t blk, int64_t nblk) {
+    constexpr int CPM = CP < 16 ? 16 : CP;
+    constexpr int M = CPM / 16;
+    constexpr int NC = 4 * M;
+    constexpr int STRIDE = sizeof(T) == 8 ? CPM + 4 : CPM + (CPM == 16 ? 32 : 16);
+    constexpr int NMAT = ACCEL ? 2 : 1;   // staged tiles: p (and the z tile before it), y'
+    constexpr int NSYM = SymBlocks<M>::N;
+    constexpr int BPW = (NSYM + 3) / 4;
+    using A4 = typename Acc4<T>::type;
+    using L = FusedLayout<CPM>;
+    using Lc = typename SpmmCfg<T, CP>::Light;
+    constexpr int NE = Lc::LANE_ELEMS;
+    constexpr int DEPTH = 4;
+    static_assert(64 % Lc::TEAMS == 0 || Lc::TEAMS >= 64, "every wave walks the same rows");
+
+    const DevState *__restrict__ st = I.st;
+    T *const *Xring = (T *const *)I.X;
+    const T *__restrict__ Y = Xring[st->role[ROLE_P]];     // Y_n: gathered and streamed
+    T *__restrict__ Yn = Xring[st->role[ROLE_N]];          // Y_{n+1}
+    T *__restrict__ Xb = Xring[st->role[ROLE_C]];          // Xbar_{n-1} -> Xbar_n
+    const T *__restrict__ Zl = (const T *)I.Z[st->role[ROLE_P]];   // long rows' S_off Y_n
+    const T *__restrict__ GYs = (const T *)I.GYs;
+    const int64_t *__restrict__ row_ptr = I.row_ptr;
+    const int32_t *__restrict__ col = I.col;
+    const T *__restrict__ val = (const T *)I.val;
+    const int64_t n = I.n, light_max = I.light_max;
+    const int c = I.c, diag_unit = I.diag_unit;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r = lane & 15, g = lane >> 4;
+    const double beta_next = ACCEL ? st->beta_next : 0.0;
+    const T tau = (T)st->tau;
+    const T bn1 = (T)(1.0 + beta_next), bn0 = (T)beta_next;
+
+    constexpr bool G_LDS = sizeof(T) == 4;
+    constexpr int GSTR = CPM + 1;
+    __shared__ T gsh[G_LDS ? CPM * GSTR : 1];
+    T gA[G_LDS ? 1 : M][G_LDS ? 1 : NC];
+    if constexpr (G_LDS) {
+        for (int e = tid; e < CPM * CPM; e += 256)
+            gsh[(e / CPM) * GSTR + e % CPM] = GYs[e];
+        __syncthreads();
+    } else {
+#pragma unroll
+        for (int a = 0; a < M; ++a)
+#pragma unroll
+            for (int s = 0; s < NC; ++s)
+                gA[a][s] = GYs[(16 * a + r) * CPM + kslot<T>(s, g)];
+    }
+    __shared__ __attribute__((aligned(16))) T lds[NMAT][64 * STRIDE];
+
+    double sc_sq = 0.0;
+    int32_t n_bad = 0;
+    doublex4 acc64[BPW];
+#pragma unroll
+    for (int k = 0; k < BPW; ++k)
+        acc64[k] = doublex4{0, 0, 0, 0};
+
+    // a row of a stream in the lane layout (padded components read as zero)
+    auto load_row = [&](const T *__restrict__ src, int64_t row, bool live, T (&out)[NC]) {
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            const int k0 = 16 * a + 4 * g;
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                out[4 * a + q] = (T)0;
+            if constexpr (sizeof(T) == 4) {
+                if (live && k0 < CP) {
+                    T t4[4];
+                    GatherLoad<T, 4>::load(src + row * CP + k0, t4);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        out[4 * a + q] = t4[q];
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int k = kslot<T>(4 * a + q, g);
+                    if (live && k < CP)
+                        out[4 * a + q] = src[row * CP + k];
+                }
+            }
+        }
+    };
+
+    const int64_t nwt = nwt_of(n);
+    for (int64_t wt = blk; wt < nwt; wt += nblk) {
+        // the lane's own rows of Y_n and Xbar_{n-1} are requested first, so
+        // these stream reads are in flight while the gathers below run
+        const int64_t row = wt * 64 + wave * 16 + r;
+        const bool live = row < n;
+        const int lrow = wave * 16 + r;
+        T y[NC], xp[NC], z[NC];
+        load_row(Y, row, live, y);
+        if constexpr (ACCEL)
+            load_row(Xb, row, live, xp);
+        // A. S_off Y_n for the tile's rows, into lds[0] (row-major, stride STRIDE)
+        __syncthreads();   // the previous tile's reads of lds are done
+        {
+            const int team = tid / Lc::TEAM, lt = tid % Lc::TEAM;
+            const int slot = lt / Lc::GS, sub = lt % Lc::GS;
+            for (int rr = team; rr < 64; rr += Lc::TEAMS) {
+                const int64_t row = wt * 64 + rr;
+                T acc[NE];
+#pragma unroll
+                for (int q = 0; q < NE; ++q)
+                    acc[q] = (T)0;
+                bool longrow = false;
+                if (row < n) {
+                    const int64_t beg = row_ptr[row], end = row_ptr[row + 1];
+                    if (end - beg > light_max)
+                        longrow = true;
+                    else
+                        team_row_sum<T, T, CP, Lc::SLOTS, DEPTH>(col, val, Y, beg, end, slot, sub, acc,
+                                                                 I.nt_from);
+                }
+                team_slot_sum<Lc::GS, Lc::TEAM>(acc);
+                if (slot == 0) {
+                    if (longrow)
+#pragma unroll
+                        for (int q = 0; q < NE; ++q)
+                            acc[q] = Zl[row * CP + sub * NE + q];
+#pragma unroll
+                    for (int q = 0; q < NE; ++q)
+                        lds[0][rr * STRIDE + sub * NE + q] = acc[q];
+                }
+            }
+        }
+        __syncthreads();
+
+        // B. the step, in the fused kernel's lane layout
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int k = kslot<T>(s, g);
+            z[s] = (live && k < CP) ? lds[0][lrow * STRIDE + k] : (T)0;
+            if (diag_unit)
+                z[s] += y[s];
+        }
+        T yg[NC];
+#pragma unroll
+        for (int a = 0; a < M; ++a) {
+            A4 acc = A4{0, 0, 0, 0};
+#pragma unroll
+            for (int s = 0; s < NC; ++s) {
+                T ga;
+                if constexpr (G_LDS)
+                    ga = gsh[(16 * a + r) * GSTR + kslot<T>(s, g)];
+                else
+                    ga = gA[a][s];
+                acc = mfma16x16x4(ga, y[s], acc);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                yg[4 * a + q] = acc[q];
+        }
+        T v[NC];
+        bool valid[NC];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int k = kslot<T>(s, g);
+            valid[s] = live && k < c;
+            const T grad = (T)(-4) * (z[s] - yg[s]);
+            v[s] = y[s] - tau * grad;
+        }
+        const double theta = simplex_threshold<T, NC>(v, valid);
+        T p[NC];
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const double w = (double)v[s] - theta;
+            p[s] = valid[s] && w > 0.0 ? (T)w : (T)0;
+            if (valid[s]) {
+                const double d = (double)p[s] - (double)y[s];
+                sc_sq += d * d;
+                if (!(v[s] == v[s]) || v[s] - v[s] != (T)0)
+                    n_bad += 1;
+            }
+        }
+
+        // C. stage p (over the z tile) and y', write them, Gram of y'
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < NC; ++s) {
+            const int k = kslot<T>(s, g);
+            lds[0][lrow * STRIDE + k] = p[s];
+            if constexpr (ACCEL)
+                lds[1][lrow * STRIDE + k] = bn1 * p[s] - bn0 * xp[s];
+        }
+        __syncthreads();
+        {
+            constexpr int PER = 16 / (int)sizeof(T);
+            constexpr int RP = CP / PER > 0 ? CP / PER : 1;
+            constexpr int PW = CP / PER > 0 ? PER : CP;   // components per piece
+            constexpr int PIECES = 16 * RP;
+            using V16 = T __attribute__((ext_vector_type(PW)));
+            const int64_t row0 = wt * 64 + wave * 16;
+#pragma unroll
+            for (int e0 = 0; e0 < PIECES; e0 += 64) {
+                const int e = e0 + lane;
+                const int lr = e / RP, kc = (e % RP) * PW;
+                if ((PIECES % 64 == 0 || e < PIECES) && row0 + lr < n) {
+                    const int li = (wave * 16 + lr) * STRIDE + kc;
+                    *reinterpret_cast<V16 *>(Xb + (row0 + lr) * CP + kc) =
+                        *reinterpret_cast<const V16 *>(&lds[0][li]);
+                    *reinterpret_cast<V16 *>(Yn + (row0 + lr) * CP + kc) =
+                        *reinterpret_cast<const V16 *>(&lds[NMAT - 1][li]);
+                }
+            }
+        }
+#pragma unroll
+        for (int kk = 0; kk < BPW; ++kk) {
+            const int kb = wave + 4 * kk;
+            if (kb < NSYM) {
+                int a, b;
+                SymBlocks<M>::ab(kb, a, b);
+                A4 acc = A4{0, 0, 0, 0};
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
+                    const T va = lds[NMAT - 1][(4 * t + g) * STRIDE + 16 * a + r];
+                    const T vb = lds[NMAT - 1][(4 * t + g) * STRIDE + 16 * b + r];
+                    acc = mfma16x16x4(va, vb, acc);
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    acc64[kk][q] += (double)acc[q];
+            }
+        }
+    }
+
+    // partials: the Gram matrix of Y_{n+1} in the second matrix slot
+    double *out = I.part_fused + blk * L::NE;
+#pragma unroll
+    for (int kk = 0; kk < BPW; ++kk) {
+        const int kb = wave + 4 * kk;
+        if (kb < NSYM) {
+            int a, b;
+            SymBlocks<M>::ab(kb, a, b);
+            double *o = out + L::MAT;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = 16 * a + mfma_row<T>(g, q), j = 16 * b + r;
+                o[i * CPM + j] = acc64[kk][q];
+                if (a != b)
+                    o[j * CPM + i] = acc64[kk][q];
+            }
+        }
+    }
+    double vals[6] = {0.0, 0.0, sc_sq, 0.0, (double)n_bad, 0.0};
+    fused_scalars_out(vals, out + 3 * L::MAT);
+}
+
+template <typename T, int CP, bool ACCEL>
+__global__ __launch_bounds__(256, (fused_min_waves<T, CP, false>())) void k_single_1(Inst I) {
+    if (inst_active(I))
+        single_body<T, CP, ACCEL>(I, blockIdx.x, gridDim.x);
+}
+
 // Deferred loss of the current iterate: the terms <x_i, (S_eff X)_i> as the
 // fused kernel forms them (same tiles, lanes, order and grid), written to
 // the same scalar slot of the same partial rows.
@@ -1530,14 +1816,19 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
     double *__restrict__ hist_r = I.hist_r;
     const int tid = threadIdx.x;
     // mode 0: initial evaluation; 1: after a trial; 2: deferred evaluation of
-    // the current iterate after the trials (nothing else changes)
+    // the current iterate after the trials (nothing else changes); 3: the
+    // read-out loss of a single-pass instance (nothing else changes)
     if (mode == 1 && !st->active)
         return;
+    // a single-pass iteration forms no loss terms; its pass leaves the Gram
+    // matrix of the next extrapolated point in the second matrix slot
+    const bool single = I.pass_kind == PASS_SINGLE;
+    const bool single_step = single && mode == 1;
     // the products' terms sum_i <x_i, (S X)_i>: workgroup partials of the
     // sparse product, combined in a fixed order (a deferred instance forms
     // them in the fused pass instead; its products write no partials)
     double tr_total = 0.0;
-    if (!I.defer) {
+    if (!I.defer && !single_step) {
         const int64_t np = (int64_t)I.g_spmm + I.g_comb;
         double a = 0.0;
 #pragma unroll 8
@@ -1554,8 +1845,8 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
         __syncthreads();
     }
     const int c = st->c;
-    const double *Gp = red_mats;                       // Gram of the new point
-    const double *Gnext = red_mats + (mode == 1 && st->accelerate ? L::MAT : 0);
+    const double *Gp = red_mats + (single_step ? L::MAT : 0);   // Gram of the new point
+    const double *Gnext = single ? Gp : red_mats + (mode == 1 && st->accelerate ? L::MAT : 0);
     const double *Mx = red_mats + 2 * L::MAT;
     const double *sc = red_mats + 3 * L::MAT;
 
@@ -1607,6 +1898,19 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
                 st->active = 0;
                 accept = 0;
             }
+        } else if (mode == 3) {
+            // single pass: the loss of the iterate being read out
+            accept = 0;
+            st->f_prev = st->f;
+            st->f = f_p;
+            st->f_known = 1;
+            if (st->iter < st->hist_cap && hist_f)
+                hist_f[st->iter] = f_p;
+            if (!(f_p == f_p) || f_p - f_p != 0.0) {
+                st->error = ERR_NONFINITE;
+                st->stop_reason = STOP_ERROR;
+                st->active = 0;
+            }
         } else if (mode == 2 || (st->defer && !st->f_known)) {
             // deferred loss of Xbar_iter: ||G||^2 saved when it was accepted
             accept = mode == 1;
@@ -1635,8 +1939,9 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
             const double tr_y = sc[FS_TRY], lin_s = sc[FS_LIN], sq = sc[FS_SQ];
             const double corr = sc[FS_CORR], bad = sc[FS_BAD];
             st->trials += 1;
-            // deferred: f_p is not this trial's loss; check what it provides
-            const double f_chk = st->defer ? gp_sq : f_p;
+            // deferred or single pass: f_p is not this trial's loss; check
+            // what it provides
+            const double f_chk = (st->defer || single) ? gp_sq : f_p;
             const bool finite = (f_chk == f_chk) && (f_chk - f_chk == 0.0) && bad == 0.0;
             if (!finite) {
                 st->error = ERR_NONFINITE;
@@ -1660,6 +1965,8 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
                 if (st->defer) {   // f(Xbar_it) follows from the next pass
                     st->f_known = 0;
                     st->gsq_c = gp_sq;
+                } else if (single) {   // f(Xbar_it) is formed at the read-out
+                    st->f_known = 0;
                 } else {
                     st->f = f_p;
                 }
@@ -1667,16 +1974,21 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
                 if (it == 1)
                     st->r1 = rr;
                 if (it < st->hist_cap) {
-                    if (hist_f && !st->defer) hist_f[it] = f_p;
+                    if (hist_f && !st->defer) hist_f[it] = single ? __longlong_as_double(0x7ff8000000000000ll) : f_p;
                     if (hist_tau) hist_tau[it] = st->tau;
                     if (hist_trials) hist_trials[it] = st->trial_in_iter;
                     if (hist_r) hist_r[it] = rr;
                 }
-                // ring: trial -> current, current -> previous, previous -> next trial
-                const int rc = st->role[ROLE_C], rp = st->role[ROLE_P], rn = st->role[ROLE_N];
-                st->role[ROLE_C] = rn;
-                st->role[ROLE_P] = rc;
-                st->role[ROLE_N] = rp;
+                if (single) {   // Xbar stays in place; Y_{n+1} becomes the current Y
+                    const int rp = st->role[ROLE_P];
+                    st->role[ROLE_P] = st->role[ROLE_N];
+                    st->role[ROLE_N] = rp;
+                } else {   // ring: trial -> current, current -> previous, previous -> next trial
+                    const int rc = st->role[ROLE_C], rp = st->role[ROLE_P], rn = st->role[ROLE_N];
+                    st->role[ROLE_C] = rn;
+                    st->role[ROLE_P] = rc;
+                    st->role[ROLE_N] = rp;
+                }
                 // inertial parameter (Alg. 4)
                 const double t_next = 0.5 * (1.0 + sqrt(1.0 + 4.0 * st->t * st->t));
                 st->beta = st->beta_next;

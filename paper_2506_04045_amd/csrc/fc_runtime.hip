@@ -367,6 +367,8 @@ struct fc_solver {
     double spec_norm = 0.0, L_thm = 0.0;
     int reorder = FC_REORDER_NONE;
     int defer = 0;              // deferred loss evaluation (fixed steps)
+    int single = 0;             // single-pass iteration (fixed steps)
+    Inst inst_long = {};        // its sparse-product pre-pass (rows longer than light_max)
     int32_t *d_perm = nullptr;  // internal row i is user row d_perm[i]
     int32_t *d_inv = nullptr;   // user row j is internal row d_inv[j]
     std::vector<void *> allocs;
@@ -485,9 +487,69 @@ fc_status launch_init_t(fc_solver *h) {
     return FC_OK;
 }
 
+// The pre-pass of a single-pass iteration: medium and heavy rows of
+// S_off Y_n into Z (light rows are summed inside the single-pass kernel).
+template <typename T, int CP>
+void launch_single_prepass(fc_solver *h) {
+    if (h->heavy.nmed + h->heavy.nheavy > 0)
+        launch_spmm<T, T, T, T, CP>(h->inst_long, (int)ROLE_P, h->stream);
+}
+
+// One single-pass iteration: the pre-pass, the single-pass kernel, the
+// reduction, the controller (events: the pre-pass between ev[0] and ev[1],
+// the single-pass kernel between ev[1] and ev[2]).
+template <typename T, int CP>
+fc_status launch_single_t(fc_solver *h, hipEvent_t *ev) {
+    constexpr int CPM = CP < 16 ? 16 : CP;
+    hipStream_t s = h->stream;
+    const Inst &I = h->inst;
+    if (ev)
+        HIPCHK(hipEventRecord(ev[0], s));
+    launch_single_prepass<T, CP>(h);
+    if (ev)
+        HIPCHK(hipEventRecord(ev[1], s));
+    if (h->accelerate)
+        hipLaunchKernelGGL((k_single_1<T, CP, true>), dim3(h->g_fused), dim3(256), 0, s, I);
+    else
+        hipLaunchKernelGGL((k_single_1<T, CP, false>), dim3(h->g_fused), dim3(256), 0, s, I);
+    if (ev)
+        HIPCHK(hipEventRecord(ev[2], s));
+    hipLaunchKernelGGL((k_reduce_fused_1<CPM>), dim3(h->g_red), dim3(256), 0, s, I);
+    if (ev)
+        HIPCHK(hipEventRecord(ev[3], s));
+    hipLaunchKernelGGL((k_control_1<T, CPM>), dim3(1), dim3(256), 0, s, I, 1);
+    if (ev)
+        HIPCHK(hipEventRecord(ev[4], s));
+    HIPCHK(hipGetLastError());
+    return FC_OK;
+}
+
+// Loss of the current iterate of a single-pass solver: its Gram matrix and
+// S_eff Xbar with the terms <x_i, (S_eff X)_i>, then the controller.
+template <typename T, int CP>
+fc_status launch_single_eval_t(fc_solver *h) {
+    constexpr int CPM = CP < 16 ? 16 : CP;
+    hipStream_t s = h->stream;
+    const int ld = CPM * CPM;
+    hipLaunchKernelGGL((k_gram<T, CP>), dim3(h->g_gram), dim3(256), 0, s, (const T *)h->X[0], h->n,
+                       h->d_part_gram, (int64_t)ld);
+    launch_reduce(h->d_part_gram, (int64_t)h->g_gram * 4, ld, ld, h->d_red_mats, s);
+    // a read-out comes after the last iteration, when the state is no longer
+    // active: the product runs stateless (ring slot 0, where Xbar stays)
+    Inst ev = h->inst;
+    ev.st = nullptr;
+    launch_spmm<T, T, T, T, CP>(ev, (int)ROLE_C, s);
+    hipLaunchKernelGGL((k_control_1<T, CPM>), dim3(1), dim3(256), 0, s, h->inst, 3);
+    HIPCHK(hipGetLastError());
+    return FC_OK;
+}
+
 fc_status launch_trial(fc_solver *h, hipEvent_t *ev = nullptr) {
     return with_cp(h->cp, [&](auto cpc) -> fc_status {
         constexpr int CP = decltype(cpc)::value;
+        if (h->single)
+            return h->prec == FC_PREC_FP64 ? launch_single_t<double, CP>(h, ev)
+                                           : launch_single_t<float, CP>(h, ev);
         if (h->prec == FC_PREC_FP64)
             return launch_trial_t<double, double, double, CP>(h, ev);
         if (h->prec == FC_PREC_FP32)
@@ -501,6 +563,9 @@ fc_status launch_trial(fc_solver *h, hipEvent_t *ev = nullptr) {
 fc_status launch_eval(fc_solver *h) {
     return with_cp(h->cp, [&](auto cpc) -> fc_status {
         constexpr int CP = decltype(cpc)::value;
+        if (h->single)
+            return h->prec == FC_PREC_FP64 ? launch_single_eval_t<double, CP>(h)
+                                           : launch_single_eval_t<float, CP>(h);
         if (h->prec == FC_PREC_FP64)
             return launch_eval_t<double, CP>(h);
         return launch_eval_t<float, CP>(h);
@@ -560,6 +625,7 @@ fc_status status_of(const fc_solver *h) {
 struct EventLog {
     std::vector<hipEvent_t> ev;
     fc_kernel_times *out = nullptr;
+    bool single = false;   // slot 0 is the pre-pass (a sparse product), slot 1 the fused pass
     ~EventLog() {
         for (hipEvent_t e : ev)
             (void)hipEventDestroy(e);
@@ -586,8 +652,8 @@ struct EventLog {
                 if (e != hipSuccess)
                     return e;
             }
-            out->fused_ms += ms[0];
-            out->spmm_ms += ms[1];
+            out->fused_ms += single ? ms[1] : ms[0];
+            out->spmm_ms += single ? ms[0] : ms[1];
             out->reduce_ms += ms[2];
             out->control_ms += ms[3];
             out->launches += 1;
@@ -626,7 +692,7 @@ fc_status run_until(fc_solver *h, int32_t target, int32_t max_iter, EventLog *lo
     }
     if (log)
         HIPCHK(log->collect());
-    if (h->defer && !h->h.f_known && h->h.error == ERR_NONE) {
+    if ((h->defer || h->single) && !h->h.f_known && h->h.error == ERR_NONE) {
         // the loss of the last accepted iterate
         st = launch_eval(h);
         if (st == FC_OK)
@@ -812,7 +878,17 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
     h->hist_cap = hist_cap;
     h->check_every = opt->check_every > 0 ? opt->check_every : 16;
     h->defer = opt->defer_loss ? 1 : 0;
+    h->single = opt->single_pass ? 1 : 0;
     h->max_iter = opt->max_iter;
+    if (h->single) {
+        if (h->backtrack)
+            return cleanup(fail(FC_ERR_UNSUPPORTED, "the single-pass iteration takes constant or scheduled steps"));
+        if (h->prec == FC_PREC_MIXED)
+            return cleanup(fail(FC_ERR_UNSUPPORTED, "the single-pass iteration runs in FP64 or FP32"));
+        if (opt->tol_loss == opt->tol_loss)
+            return cleanup(fail(FC_ERR_UNSUPPORTED, "the single-pass iteration has no per-iteration loss (tol_loss must be NaN)"));
+        h->defer = 0;
+    }
     hipStream_t s = h->stream;
 
     if (opt->validate) {
@@ -865,6 +941,14 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
     const size_t esz = h->prec == FC_PREC_FP64 ? 8 : 4;
     const size_t mat_bytes = (size_t)h->n * h->cp * esz;
     for (int k = 0; k < 3; ++k) {
+        // the single-pass iteration keeps one product buffer: the long rows
+        // of S Y_n within an iteration, S Xbar at a read-out
+        if (h->single && k > 0) {
+            if (h->alloc(&h->X[k], mat_bytes) != hipSuccess)
+                return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "iterate buffers"));
+            h->Z[k] = h->Z[0];
+            continue;
+        }
         if (h->alloc(&h->X[k], mat_bytes) != hipSuccess || h->alloc(&h->Z[k], mat_bytes) != hipSuccess)
             return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "iterate buffers"));
         if (h->prec == FC_PREC_MIXED &&
@@ -956,6 +1040,7 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
         I.hist_trials = h->d_hist_trials;
         I.sched = nullptr;
         I.defer = h->defer;
+        I.pass_kind = h->single ? PASS_SINGLE : PASS_DEFAULT;
         // relabelled FP32 instances whose rows fill whole 128-byte lines: the
         // rows past the first 256 MB of X (the size of MI355X's Infinity
         // Cache; the most-gathered rows come first) are gathered
@@ -968,6 +1053,11 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
                             cache_rows < h->n
                         ? cache_rows
                         : 0;
+    }
+    if (h->single) {   // the pre-pass: stored products of the long rows only
+        h->inst_long = h->inst;
+        h->inst_long.defer = 1;
+        h->inst_long.pass_kind = PASS_LONG;
     }
     if (hipMemsetAsync(h->d_red_mats, 0, sizeof(double) * ne, s) != hipSuccess ||
         hipMemsetAsync(h->d_hist_trials, 0, sizeof(int32_t) * h->hist_cap, s) != hipSuccess)
@@ -983,6 +1073,7 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
             if (!(opt->step_schedule[k] > 0.0))
                 return cleanup(fail(FC_ERR_INVALID_ARG, "step schedule entries must be > 0"));
         h->inst.sched = h->d_sched;
+        h->inst_long.sched = h->d_sched;
     }
 
     // Xbar_0 (the other two ring slots start as copies of it)
@@ -1120,6 +1211,7 @@ fc_status fc_step_profiled(fc_solver *h, int32_t iters, fc_info *info, fc_kernel
     if (iters > 0) {
         EventLog log;
         log.out = times;
+        log.single = h->single != 0;
         const int64_t target = (int64_t)h->h.iter + iters;
         st = run_until(h, (int32_t)(target > INT_MAX ? INT_MAX : target), INT_MAX, &log);
     }
@@ -1215,7 +1307,7 @@ struct CkptHeader {
     int64_t n;
     int32_t c, cp, prec, accelerate, backtrack, diag;
     int32_t hist_len, reorder;
-    int32_t defer, reserved;
+    int32_t defer, reserved;   // reserved: the single-pass flag
     DevState st;
 };
 constexpr uint64_t CKPT_MAGIC = 0x3130545043434646ull;  // "FFCCPT01"
@@ -1259,6 +1351,7 @@ fc_status fc_get_state(const fc_solver *h, void *buf, size_t *bytes) {
     hd.diag = (int32_t)h->diag;
     hd.reorder = h->reorder;
     hd.defer = h->defer;
+    hd.reserved = h->single;
     hd.hist_len = hist_len;
     hd.st = h->h;
     char *p = (char *)buf;
@@ -1298,7 +1391,7 @@ fc_status fc_set_state(fc_solver *h, const void *buf, size_t bytes) {
         return fail(FC_ERR_INVALID_ARG, "not a checkpoint of this library version");
     if (hd.n != h->n || hd.c != h->c || hd.cp != h->cp || hd.prec != (int32_t)h->prec ||
         hd.accelerate != h->accelerate || hd.backtrack != h->backtrack || hd.diag != (int32_t)h->diag ||
-        hd.reorder != h->reorder || hd.defer != h->defer)
+        hd.reorder != h->reorder || hd.defer != h->defer || hd.reserved != h->single)
         return fail(FC_ERR_INVALID_ARG, "checkpoint was taken from a solver with other n, c or options");
     if (hd.hist_len < 1 || hd.hist_len > h->hist_cap || bytes < ckpt_bytes(h, hd.hist_len))
         return fail(FC_ERR_INVALID_ARG, "checkpoint buffer truncated");

@@ -34,7 +34,10 @@ def fc():
     return fc
 
 
-def _check_first_step(fc, wl, precision, val_for_oracle, seed, configs=(("degree", True),)):
+BENCH = dict(reorder="degree", defer_loss=True)   # the benchmark's launch configuration
+
+
+def _check_first_step(fc, wl, precision, val_for_oracle, seed, configs=(BENCH,)):
     rows = _sample(wl.row_ptr, seed)
     sub_rp, sub_ci, sub_v = _sub_csr(wl.row_ptr, wl.col_idx, wl.val, rows)
     if val_for_oracle is not None:
@@ -52,21 +55,21 @@ def _check_first_step(fc, wl, precision, val_for_oracle, seed, configs=(("degree
         print(f"full-size product, {rows.size} sampled rows: normwise {err:.2e}")
         assert err <= 1e-5
 
-    # one step in the benchmark's launch configuration (articles relabelled by
-    # degree inside the solver, deferred loss evaluation), and in the plain one
+    # one step in the benchmark's launch configurations (articles relabelled by
+    # degree inside the solver; deferred loss evaluation, or the single-pass
+    # iteration), and in the plain one
     x_ref = oracle.step_rows(rows, sub_rp, sub_ci, sub_v, True, U0, TAU)
     moved = np.abs(x_ref - U0[rows]).max()
-    for reorder, defer in configs:
+    for kw in configs:
         with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, precision=precision,
-                       accelerate=True, step=TAU, reorder=reorder, defer_loss=defer) as s:
+                       accelerate=True, step=TAU, **kw) as s:
             s.step(1)
             U1 = s.get_u()
             x_gpu = U1[torch.from_numpy(rows).cuda()].double().cpu().numpy()
             del U1
         du = np.abs(x_gpu - x_ref).max()
-        print(f"full-size first step ({precision}, relabelling {reorder}, deferred loss "
-              f"{defer}), {rows.size} sampled rows: max|dU| {du:.2e} (the step moves entries "
-              f"by up to {moved:.2e})")
+        print(f"full-size first step ({precision}, {kw}), {rows.size} sampled rows: "
+              f"max|dU| {du:.2e} (the step moves entries by up to {moved:.2e})")
         # FP32 iterates of magnitude <= 1 carry ulps of at most 6e-8; the
         # step itself moves entries by about 4 tau n u_k / (c (c + 1)) ~ 1e-5
         assert du <= (1e-7 if precision == "fp32" else 5e-7)
@@ -76,7 +79,8 @@ def _check_first_step(fc, wl, precision, val_for_oracle, seed, configs=(("degree
 def test_power_law_full_size_fp32(fc):
     wl = W.config_full_power_law(device="cuda")
     torch.cuda.synchronize()
-    _check_first_step(fc, wl, "fp32", None, seed=1, configs=(("degree", True), ("none", False)))
+    _check_first_step(fc, wl, "fp32", None, seed=1,
+                      configs=(BENCH, dict(reorder="degree", single_pass=True), dict(reorder="none")))
 
     # later iterations: simplex columns and bitwise-identical reruns
     def run(k):
@@ -89,7 +93,17 @@ def test_power_law_full_size_fp32(fc):
     assert float((Ua.double().sum(1) - 1).abs().max()) <= 1e-5
     info_b, Ub = run(12)
     assert info_a.f == info_b.f and torch.equal(Ua, Ub)
-    del Ua, Ub, wl
+    del Ub
+    # the single-pass iteration follows the same iterates (FP32 rounding
+    # differs only in how Y and S Y are formed)
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, accelerate=True, step=0.0,
+                   reorder="degree", single_pass=True) as s:
+        info_c = s.step(12)
+        du = float((s.get_u() - Ua).abs().max())
+    print(f"full-size 12 iterations, single pass vs deferred mode: max|dU| {du:.2e}, "
+          f"f {info_c.f:.9e} vs {info_a.f:.9e}")
+    assert du <= 1e-6 and abs(info_c.f - info_a.f) <= 1e-6 * abs(info_a.f)
+    del Ua, wl
     torch.cuda.empty_cache()
 
 
