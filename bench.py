@@ -180,6 +180,21 @@ def _median_iteration(res) -> float:
     return float(np.median(secs[np.isfinite(secs)]))
 
 
+def measured_mfma(workload_key: str):
+    """Matrix-core utilisation per kernel from the committed counter summary
+    (profiles/mfma.json), or None when the kernel source changed since."""
+    path = os.path.join(PROFILES, "mfma.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        ent = json.load(open(path))[workload_key]
+    except (KeyError, ValueError):
+        return None
+    if ent.get("kernel_source_sha") != kernel_source_sha():
+        return None
+    return ent.get("kernels")
+
+
 def cpu_baseline(args, c: int, n_full: int, nnz_full: int) -> dict:
     """The FP64 oracle (plain C + OpenMP, as committed) timed on the host
     cores: the median wall time per iteration over iterations 2..K.
@@ -670,6 +685,10 @@ def main() -> int:
     wkey = (f"powerlaw_n{n}_c{c}_{prec}_{args.reorder}" + ("_deferred" if defer else "")
             + ("_single" if single else ""))
     traffic = measured_traffic(dom, wkey)
+    mfma = measured_mfma(wkey)
+    if mfma:
+        for k, v in mfma.items():
+            kernels.setdefault(k, {})["mfma"] = v
     roofline = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["achieved_GBps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": kernels[dom]["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic}
