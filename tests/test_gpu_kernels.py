@@ -6,6 +6,8 @@ Tolerances: FP64 kernels agree to rounding (1e-12 relative); FP32 kernels
 to a normwise relative error of 1e-5, computed against the oracle run in
 double on the same FP32-representable inputs.
 """
+import ctypes
+
 import numpy as np
 import pytest
 import torch
@@ -192,3 +194,23 @@ def test_spmm_power_law_rows_of_every_class(fc):
     ref32 = oracle.x_s(rp, ci, v32.astype(np.float64), True, U32.astype(np.float64))
     z32 = fc.spmm(*csr_to_dev(rp, ci, v32, torch.float32), dev(U32)).cpu().numpy()
     assert normwise(z32, ref32) <= 1e-5
+
+
+def test_gather_probe_runs_and_checks_its_arguments(fc):
+    """fc_gather_probe (a memory-system measurement, not a step of the
+    method): it times a flat pass of row gathers and rejects bad sizes."""
+    from paper_2506_04045_amd import _native as N
+    n = 50_000
+    U = torch.rand(n, 32, device="cuda")
+    col = torch.randint(0, n, (400_000,), device="cuda", dtype=torch.int32)
+    ms = fc.gather_probe(col, U, wg_per_cu=4, reps=3)
+    assert 0.0 < ms < 1000.0
+    ms_bf16 = fc.gather_probe(col, U.to(torch.bfloat16), wg_per_cu=4, reps=3)
+    assert 0.0 < ms_bf16 < 1000.0
+    lib = N.load()
+    out = ctypes.c_double(0.0)
+    for nnz, rows, rb, w, reps in ((0, n, 128, 4, 1), (10, 0, 128, 4, 1), (10, n, 96, 4, 1),
+                                   (10, n, 128, 0, 1), (10, n, 128, 65, 1), (10, n, 128, 4, 0)):
+        st = lib.fc_gather_probe(col.data_ptr(), nnz, U.data_ptr(), rows, rb, w, reps, None,
+                                 ctypes.byref(out))
+        assert st == 1, (nnz, rows, rb, w, reps)
