@@ -319,7 +319,10 @@ def serve_bench(args) -> dict:
         del sample
         log(f"serving: tuned schedule {sched} ({tuned['runs']} runs, "
             f"{tuning['seconds']:.1f} s, sample at {tuned['solves_per_s']:.1f} solves/s)")
-    out = {"requests": R, "slots": args.serve_slots, "solo_max": args.serve_solo,
+    out = {"requests": R,
+           "stop_rule": ("backtracking FISTA until r_n <= 1e-4 r_1 (the gradient-mapping norm "
+                         "relative to its first value) or 300 iterations"),
+           "slots": args.serve_slots, "solo_max": args.serve_solo,
            "ticks_per_poll": sched["ticks_per_poll"],
            "graph": bool(sched["use_graph"]), "launch_table": {"grid_fused": sched["grid_fused"],
                                                              "grid_spmm": sched["grid_spmm"]},
