@@ -69,11 +69,14 @@ def _serve(fc, reqs, server_kw=None, stagger=None, **kw):
     return done
 
 
+@pytest.mark.parametrize("solo_max", [0, 4])
 @pytest.mark.parametrize("use_graph", [True, False])
-def test_results_are_the_same_alone_and_in_the_mix(fc, use_graph):
+def test_results_are_the_same_alone_and_in_the_mix(fc, use_graph, solo_max):
+    """solo_max = 0: every request batched; 4: the first ones run in the solo
+    lane while few are active, the others join the batched kernels."""
     reqs = _requests(14)
     alone = [_alone(fc, wl) for wl in reqs]
-    served = _serve(fc, reqs, dict(use_graph=use_graph, ticks_per_poll=4))
+    served = _serve(fc, reqs, dict(use_graph=use_graph, ticks_per_poll=4, solo_max=solo_max))
     for i, wl in enumerate(reqs):
         r, U = served[i]
         info, U_ref = alone[i]
