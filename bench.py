@@ -572,7 +572,7 @@ def main() -> int:
     ap.add_argument("--cpu-sample-n", type=int, default=1_000_000)
     ap.add_argument("--cpu-iters", type=int, default=8,
                     help="oracle iterations on the power-law sample (median of 2..K)")
-    ap.add_argument("--cpu-medium-iters", type=int, default=12,
+    ap.add_argument("--cpu-medium-iters", type=int, default=20,
                     help="oracle iterations on the n = 1e6 configuration (median of 2..K)")
     ap.add_argument("--serve-requests", type=int, default=4096,
                     help="requests of the serving measurement (0 disables it)")
