@@ -1800,10 +1800,26 @@ template <int CPM> __global__ __launch_bounds__(256) void k_reduce_fused_entry(I
 // acceptance).  mode 0: initialisation after Gram + product of Xbar_0;
 // mode 1: after the fused kernel and the product of the trial point.
 // ---------------------------------------------------------------------------
+// Sum of one double per thread of a 256-thread workgroup in a fixed order:
+// a shuffle tree in each wave (lane 0's result), then the four waves in
+// order.  Every thread returns the same value.
+__device__ __forceinline__ double block_sum_256(double v) {
+    __shared__ double wsum[4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        v += shfl_xor_d(v, off);
+    if (lane == 0)
+        wsum[wave] = v;
+    __syncthreads();
+    const double r = ((wsum[0] + wsum[1]) + wsum[2]) + wsum[3];
+    __syncthreads();   // wsum is reused by the next call
+    return r;
+}
+
 template <typename T, int CPM>
 __device__ __forceinline__ void control_body(const Inst &I, int mode) {
     using L = FusedLayout<CPM>;
-    __shared__ double sh[256];
     __shared__ int decision;
     DevState *__restrict__ st = I.st;
     const double *__restrict__ red_mats = I.red_mats;
@@ -1834,15 +1850,7 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
 #pragma unroll 8
         for (int64_t q = tid; q < np; q += 256)   // loads run ahead, adds stay in order
             a += I.part_spmm[q];
-        sh[tid] = a;
-        __syncthreads();
-        for (int s = 128; s > 0; s >>= 1) {
-            if (tid < s)
-                sh[tid] += sh[tid + s];
-            __syncthreads();
-        }
-        tr_total = sh[0];
-        __syncthreads();
+        tr_total = block_sum_256(a);
     }
     const int c = st->c;
     const double *Gp = red_mats + (single_step ? L::MAT : 0);   // Gram of the new point
@@ -1857,24 +1865,8 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
         if (mode == 1 && st->backtrack)
             a_m += Mx[e] * (Gp[e] + GY64[e]);
     }
-    sh[tid] = a_sq;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s)
-            sh[tid] += sh[tid + s];
-        __syncthreads();
-    }
-    const double gp_sq = sh[0];
-    __syncthreads();
-    sh[tid] = a_m;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s)
-            sh[tid] += sh[tid + s];
-        __syncthreads();
-    }
-    const double m_dot = sh[0];
-    __syncthreads();
+    const double gp_sq = block_sum_256(a_sq);
+    const double m_dot = mode == 1 && st->backtrack ? block_sum_256(a_m) : 0.0;
 
     if (tid == 0) {
         // deferred: the products carry no terms; the fused kernel (or the
@@ -2048,14 +2040,7 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
         if (i < c && j < c)
             msum += Gnext[e];
     }
-    sh[tid] = msum;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-        if (tid < s)
-            sh[tid] += sh[tid + s];
-        __syncthreads();
-    }
-    const double mu = sh[0] / ((double)c * (double)c);
+    const double mu = block_sum_256(msum) / ((double)c * (double)c);
     for (int e = tid; e < CPM * CPM; e += 256) {
         const int i = e / CPM, j = e % CPM;
         const double gv = Gnext[e];
