@@ -299,7 +299,7 @@ def serve_bench(args) -> dict:
     mu_seq = R / sum(service)
     log(f"serving: sequential {mu_seq:.1f} solves/s")
     sched = dict(ticks_per_poll=args.serve_ticks, use_graph=bool(args.serve_graph),
-                 grid_fused=None, grid_spmm=None)
+                 grid_fused=None, grid_spmm=None, spmm_depth=None)
     tuning = None
     if args.serve_tune > 0:
         # the autotuner runs on its own sample of the same mix (request ids
@@ -312,7 +312,8 @@ def serve_bench(args) -> dict:
                                max_active=args.serve_slots, hbm_budget=args.serve_budget_gb * 2**30,
                                ticks_per_poll=args.serve_ticks, use_graph=bool(args.serve_graph),
                                solo_max=args.serve_solo)
-        sched = {k: tuned[k] for k in ("ticks_per_poll", "use_graph", "grid_fused", "grid_spmm")}
+        sched = {k: tuned[k] for k in ("ticks_per_poll", "use_graph", "grid_fused", "grid_spmm",
+                                       "spmm_depth")}
         tuning = {"sample_requests": args.serve_tune, "server_runs": tuned["runs"],
                   "seconds": time.perf_counter() - t0,
                   "sample_solves_per_s": tuned["solves_per_s"]}
@@ -325,7 +326,8 @@ def serve_bench(args) -> dict:
            "slots": args.serve_slots, "solo_max": args.serve_solo,
            "ticks_per_poll": sched["ticks_per_poll"],
            "graph": bool(sched["use_graph"]), "launch_table": {"grid_fused": sched["grid_fused"],
-                                                             "grid_spmm": sched["grid_spmm"]},
+                                                             "grid_spmm": sched["grid_spmm"],
+                                                             "spmm_depth": sched["spmm_depth"]},
            "autotuner": tuning,
            "sequential_fp32": {"solves_per_s": mu_seq}, "loads": []}
     for li, load in enumerate(float(x) for x in str(args.serve_load).split(",")):

@@ -383,6 +383,11 @@ typedef struct {
        chunks by events instead of a poll of every stream.  0 batches every
        request. */
     int32_t solo_max;
+    /* Tile shape of the batched sparse product per padded width: gathers
+       each lane slot keeps in flight (2, 4 or 8; 0 = built-in 4).  Every
+       slot adds its nonzeros in the same order whatever this is, so it
+       changes the speed, never a result; fc_server_tune measures it. */
+    int32_t spmm_depth[5];
     int32_t reserved;
 } fc_server_opts;
 
@@ -450,8 +455,8 @@ void fc_server_destroy(fc_server *sv);
  * *base with candidate schedules and keeps the fastest, by coordinate
  * search: first graph replay (off, on) x ticks_per_poll (4, 8, 16, 32) on
  * all requests, then for each padded width present in the sample
- * grid_fused (1, 2, 4) and grid_spmm (4, 8, 16, 32) on that width's
- * requests alone.  A candidate's time runs from the first submission to the
+ * grid_fused (1, 2, 4), grid_spmm (4, 8, 16, 32) and the sparse product's
+ * tile shape spmm_depth (2, 4, 8) on that width's requests alone.  A candidate's time runs from the first submission to the
  * last result (set-up included), all requests submitted at once.  Every run
  * must return, for every request, the same status, iteration and trial
  * counts and bitwise the same final loss as the first run; otherwise

@@ -241,7 +241,7 @@ class Result:
 
 
 def _server_options(max_active, hbm_budget, ticks_per_poll, use_graph, grid_fused=None,
-                    grid_spmm=None, solo_max=None) -> N.ServerOpts:
+                    grid_spmm=None, solo_max=None, spmm_depth=None) -> N.ServerOpts:
     o = N.default_server_options()
     if solo_max is not None:
         o.solo_max = int(solo_max)
@@ -249,7 +249,8 @@ def _server_options(max_active, hbm_budget, ticks_per_poll, use_graph, grid_fuse
     o.hbm_budget = float(hbm_budget)
     o.ticks_per_poll = int(ticks_per_poll)
     o.use_graph = int(bool(use_graph))
-    for name, vals in (("grid_fused", grid_fused), ("grid_spmm", grid_spmm)):
+    for name, vals in (("grid_fused", grid_fused), ("grid_spmm", grid_spmm),
+                       ("spmm_depth", spmm_depth)):
         if vals is not None:
             vals = [int(v) for v in vals]
             if len(vals) != 5:
@@ -263,7 +264,7 @@ def tune_server(requests, max_active: int = 64, hbm_budget: float = 32.0 * 2**30
                 solo_max: int | None = None) -> dict:
     """fc_server_tune on sample requests, each a dict with row_ptr, col_idx,
     val, c, U0 (or None) and solver options as Solver takes them.  Returns
-    the chosen schedule (ticks_per_poll, use_graph, grid_fused, grid_spmm:
+    the chosen schedule (ticks_per_poll, use_graph, grid_fused, grid_spmm, spmm_depth:
     keyword arguments of Server), the rate of the final run and the number
     of server runs."""
     lib = N.load()
@@ -301,6 +302,7 @@ def tune_server(requests, max_active: int = 64, hbm_budget: float = 32.0 * 2**30
                                ctypes.byref(best), ctypes.byref(rate), ctypes.byref(runs)))
     return dict(ticks_per_poll=int(best.ticks_per_poll), use_graph=bool(best.use_graph),
                 grid_fused=list(best.grid_fused), grid_spmm=list(best.grid_spmm),
+                spmm_depth=list(best.spmm_depth),
                 solves_per_s=float(rate.value), runs=int(runs.value))
 
 
@@ -310,15 +312,17 @@ class Server:
 
     def __init__(self, max_active: int = 64, hbm_budget: float = 32.0 * 2**30,
                  ticks_per_poll: int = 16, use_graph: bool = False, grid_fused=None,
-                 grid_spmm=None, stream=None, solo_max: int | None = None):
+                 grid_spmm=None, stream=None, solo_max: int | None = None, spmm_depth=None):
         """grid_fused / grid_spmm: the launch table, five workgroups-per-CU
         entries for padded widths 4, 8, 16, 32, 64 (0 = built-in), as
         tune_server returns it.  solo_max: active requests up to which a new
         request runs unbatched on a stream of its own (None = the library's
-        default, 4; 0 batches every request)."""
+        default, 4; 0 batches every request).  spmm_depth: the batched sparse
+        product's gathers in flight per slot for each padded width (2, 4 or
+        8; 0 = built-in 4), a tile shape that changes no result."""
         lib = N.load()
         o = _server_options(max_active, hbm_budget, ticks_per_poll, use_graph, grid_fused,
-                            grid_spmm, solo_max)
+                            grid_spmm, solo_max, spmm_depth)
         h = ctypes.c_void_p()
         N.check(lib.fc_server_create(ctypes.byref(o), None if stream is None
                                      else int(stream.cuda_stream), ctypes.byref(h)))

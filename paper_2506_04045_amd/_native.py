@@ -75,7 +75,7 @@ class ServerOpts(ctypes.Structure):
                 ("hbm_budget", ctypes.c_double), ("ticks_per_poll", ctypes.c_int32),
                 ("use_graph", ctypes.c_int32), ("grid_fused", ctypes.c_int32 * 5),
                 ("grid_spmm", ctypes.c_int32 * 5), ("solo_max", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("spmm_depth", ctypes.c_int32 * 5), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

@@ -711,13 +711,14 @@ __device__ __forceinline__ double row_epilogue(bool live, int slot, int sub, int
 // TU: type of the gathered rows (f64, f32 or bf16); TZ: output type;
 // TX: type of the row u_i used by the epilogue (the master copy);
 // VS: type of the stored values.
-template <typename TU, typename TZ, typename TX, typename VS, int CP>
+// DEPTH: gathers each slot keeps in flight.  A slot still adds its nonzeros
+// in increasing order whatever DEPTH is, so DEPTH changes speed, never a sum.
+template <typename TU, typename TZ, typename TX, typename VS, int CP, int DEPTH = 4>
 __device__ __forceinline__ void spmm_body(const Inst &I, int role, int64_t blk, int64_t nblk) {
     using Lc = typename SpmmCfg<TU, CP>::Light;
     using Wc = typename SpmmCfg<TU, CP>::Wide;
     using TA = typename AccumOf<TU>::type;
     constexpr int NE = Lc::LANE_ELEMS;
-    constexpr int DEPTH = 4;
     static_assert(Lc::GS == Wc::GS, "both team shapes split a row the same way");
     const int slot_role = ring_slot(I, role);
     const TX *__restrict__ X = (const TX *)I.X[slot_role];
@@ -810,7 +811,7 @@ __global__ __launch_bounds__(256) void k_spmm_1(Inst I, int role) {
     if (inst_active(I))
         spmm_body<TU, TZ, TX, VS, CP>(I, role, blockIdx.x, gridDim.x);
 }
-template <typename TU, typename TZ, typename TX, typename VS, int CP>
+template <typename TU, typename TZ, typename TX, typename VS, int CP, int DEPTH = 4>
 __global__ __launch_bounds__(256) void k_spmm_b(const Inst *__restrict__ insts,
                                                 const VBlk *__restrict__ tab,
                                                 const int32_t *__restrict__ count, int role) {
@@ -819,7 +820,7 @@ __global__ __launch_bounds__(256) void k_spmm_b(const Inst *__restrict__ insts,
         const VBlk t = tab[vb];
         const Inst &I = insts[t.inst];
         if (inst_active(I))
-            spmm_body<TU, TZ, TX, VS, CP>(I, role, t.blk, I.g_spmm);
+            spmm_body<TU, TZ, TX, VS, CP, DEPTH>(I, role, t.blk, I.g_spmm);
     }
 }
 

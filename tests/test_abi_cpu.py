@@ -50,9 +50,9 @@ def test_struct_layouts(N):
     assert o.precision == N.FC_PREC_FP32 and o.diag == N.FC_DIAG_UNIT and o.accelerate == 1
     assert o.tol_loss != o.tol_loss  # NaN disables the loss stop by default
     so = N.default_server_options()
-    assert so.struct_size == ctypes.sizeof(N.ServerOpts) == 72
+    assert so.struct_size == ctypes.sizeof(N.ServerOpts) == 96
     assert list(so.grid_fused) == [0] * 5 and list(so.grid_spmm) == [0] * 5
-    assert so.solo_max == 4
+    assert list(so.spmm_depth) == [0] * 5 and so.solo_max == 4
 
 
 def test_server_argument_errors_before_device_work(N):

@@ -262,3 +262,16 @@ def test_cancel_queued_and_running_requests(fc):
         assert seen[1].status == cancelled and seen[1].iter < budget
         sv.cancel(10)                        # already finished: left as it is
         assert sv.poll(16, timeout_us=0) == []
+
+
+@pytest.mark.parametrize("depths", [[2, 8, 2, 8, 2], [8, 2, 8, 2, 8]])
+def test_spmm_tile_shape_changes_no_result(fc, depths):
+    """The tuned tile shape of the batched sparse product (gathers in flight
+    per slot) changes speed only: every request, all batched, bitwise equals
+    its solo run."""
+    reqs = _requests(10, seed0=1300)
+    alone = [_alone(fc, wl) for wl in reqs]
+    served = _serve(fc, reqs, dict(ticks_per_poll=4, solo_max=0, spmm_depth=depths))
+    for i in range(len(reqs)):
+        r, U = served[i]
+        assert r.status == 0 and r.f == alone[i][0].f and np.array_equal(U, alone[i][1]), i
