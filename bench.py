@@ -112,6 +112,44 @@ def degree_relabelled_columns(row_ptr, col_idx, chunk_rows: int = 1 << 23):
     return out, inv
 
 
+def block_column_reuse(row_ptr, col_rel, rows_per_block: int = 64, sample_blocks: int = 200_000,
+                       seed: int = 3) -> dict:
+    """What LDS-staged column tiles could save: over a uniform sample of
+    blocks of consecutive (relabelled) rows, the share of the blocks'
+    nonzeros whose column already occurred in the same block -- the gathers
+    a block that stages each distinct row of U once would not repeat -- and
+    the share of those repeats that fall on the 32,768 most gathered rows
+    (4 MB at c = 32, what one XCD's L2 holds; hits there already)."""
+    import torch
+    n = row_ptr.numel() - 1
+    deg = (row_ptr[1:] - row_ptr[:-1])
+    perm = torch.sort(-deg, stable=True).indices
+    rp_rel = torch.zeros(n + 1, dtype=torch.int64, device=row_ptr.device)
+    rp_rel[1:] = torch.cumsum(deg[perm], 0)
+    nblk = (n + rows_per_block - 1) // rows_per_block
+    g = torch.Generator(device=row_ptr.device).manual_seed(seed)
+    blocks = torch.randperm(nblk, generator=g, device=row_ptr.device)[:sample_blocks]
+    lo = rp_rel[blocks * rows_per_block]
+    hi = rp_rel[torch.clamp((blocks + 1) * rows_per_block, max=n)]
+    lens = hi - lo
+    total = int(lens.sum())
+    first = torch.cumsum(lens, 0) - lens
+    idx = lo.repeat_interleave(lens, output_size=total) + (
+        torch.arange(total, device=row_ptr.device) - first.repeat_interleave(lens, output_size=total))
+    cols = col_rel[idx].long()
+    bid = torch.arange(blocks.numel(), device=row_ptr.device).repeat_interleave(lens, output_size=total)
+    key, _ = torch.sort(bid * n + cols)
+    dup = torch.zeros(total, dtype=torch.bool, device=row_ptr.device)
+    dup[1:] = key[1:] == key[:-1]
+    dup_cols = key[dup] % n
+    repeats = int(dup.sum())
+    hot = int((dup_cols < 32768).sum())
+    del perm, rp_rel, idx, cols, bid, key, dup, dup_cols
+    return {"rows_per_block": rows_per_block, "blocks_sampled": int(blocks.numel()),
+            "nonzeros_sampled": total, "repeated_columns_share": repeats / max(1, total),
+            "repeats_on_32768_hottest_rows_share": hot / max(1, repeats)}
+
+
 def gather_ceiling(args, wl, c: int) -> dict:
     """The memory system's rate on the sparse product's gathers: a flat pass
     that only gathers row col[e] of an n x c matrix for every stored nonzero
@@ -142,6 +180,11 @@ def gather_ceiling(args, wl, c: int) -> dict:
         return runs[w]
 
     out["relabelled_fp32_ms"] = best(col_rel, U32, "relabelled_fp32")
+    out["lds_column_tiles"] = block_column_reuse(wl.row_ptr, col_rel)
+    log(f"gather ceiling: columns repeated within 64-row blocks "
+        f"{100 * out['lds_column_tiles']['repeated_columns_share']:.2f} % of the nonzeros, "
+        f"{100 * out['lds_column_tiles']['repeats_on_32768_hottest_rows_share']:.1f} % of them on the "
+        f"32,768 most gathered rows")
     best(wl.col_idx, U32, "generator_order_fp32")
     Ub = U32.to(torch.bfloat16)
     best(col_rel, Ub, "relabelled_bf16")
