@@ -89,9 +89,19 @@ def degree_relabelled_columns(row_ptr, col_idx, chunk_rows: int = 1 << 23):
     descending-degree order (ties by index), each row's nonzeros in their
     stored order, columns renumbered the same way (torch, on the GPU)."""
     import torch
-    n = row_ptr.numel() - 1
     deg = row_ptr[1:] - row_ptr[:-1]
     perm = torch.sort(-deg, stable=True).indices
+    del deg
+    return relabelled_columns(row_ptr, col_idx, perm, chunk_rows)
+
+
+def relabelled_columns(row_ptr, col_idx, perm, chunk_rows: int = 1 << 23):
+    """The column sequence of the product under the renumbering whose new row
+    k is old row perm[k]: rows in the new order, each row's nonzeros in their
+    stored order, columns renumbered the same way."""
+    import torch
+    n = row_ptr.numel() - 1
+    deg = row_ptr[1:] - row_ptr[:-1]
     inv = torch.empty(n, dtype=torch.int32, device=row_ptr.device)
     inv[perm] = torch.arange(n, dtype=torch.int32, device=row_ptr.device)
     out = torch.empty_like(col_idx)
@@ -112,18 +122,93 @@ def degree_relabelled_columns(row_ptr, col_idx, chunk_rows: int = 1 << 23):
     return out, inv
 
 
+def cuthill_mckee_order(row_ptr, col_idx, edge_chunk: int = 1 << 27):
+    """Breadth-first (Cuthill-McKee) order of the largest component reached
+    from the highest-degree row: level by level, each new row placed after the
+    rows of the previous level in the order of its first-placed neighbour,
+    ties by ascending degree.  Rows the search does not reach (other
+    components, empty rows) follow in descending-degree order.  Returns perm
+    (new row k is old row perm[k]) and the number of rows reached."""
+    import torch
+    dev = row_ptr.device
+    n = row_ptr.numel() - 1
+    deg = row_ptr[1:] - row_ptr[:-1]
+    pos = torch.full((n,), -1, dtype=torch.int64, device=dev)
+    best = torch.full((n,), n, dtype=torch.int64, device=dev)
+    start = int(torch.argmax(deg))
+    order = [torch.tensor([start], dtype=torch.int64, device=dev)]
+    pos[start] = 0
+    placed = 1
+    frontier = order[0]
+    fpos0 = 0
+    maxdeg = int(deg.max())
+    while frontier.numel() > 0:
+        fdeg = deg[frontier]
+        cum = torch.cumsum(fdeg, 0)
+        a = 0
+        while a < frontier.numel():   # frontier rows in chunks of about edge_chunk nonzeros
+            base = int(cum[a - 1]) if a > 0 else 0
+            b = int(torch.searchsorted(cum, base + edge_chunk, right=True))
+            b = max(b, a + 1)
+            rows, lens = frontier[a:b], fdeg[a:b]
+            total = int(lens.sum())
+            if total:
+                first = torch.cumsum(lens, 0) - lens
+                src = (row_ptr[rows] - first).repeat_interleave(lens, output_size=total)
+                src += torch.arange(total, device=dev)
+                nbr = col_idx[src].long()
+                par = (fpos0 + a + torch.arange(b - a, device=dev)).repeat_interleave(
+                    lens, output_size=total)
+                fresh = pos[nbr] < 0
+                best.scatter_reduce_(0, nbr[fresh], par[fresh], reduce="amin")
+                del src, nbr, par, fresh, first
+            a = b
+        new = torch.nonzero((pos < 0) & (best < n)).flatten()
+        key = best[new] * (maxdeg + 1) + deg[new]
+        new = new[torch.sort(key, stable=True).indices]
+        pos[new] = placed + torch.arange(new.numel(), device=dev)
+        order.append(new)
+        fpos0 = placed
+        placed += new.numel()
+        frontier = new
+    reached = placed
+    rest = torch.nonzero(pos < 0).flatten()
+    rest = rest[torch.sort(-deg[rest], stable=True).indices]
+    order.append(rest)
+    perm = torch.cat(order)
+    del pos, best, deg
+    return perm, reached
+
+
+def community_order(wl, seed: int, c: int):
+    """Rows grouped by their dominant planted community (the generator's own
+    planting, regenerated from the seed), descending degree within a group."""
+    import torch
+    import workloads as W
+    cm = W.planted_communities(wl.n, c, 3, 0.2, seed, device=wl.row_ptr.device)
+    dom = cm.ids.gather(1, torch.argmax(cm.w, dim=1, keepdim=True)).flatten().long()
+    del cm
+    deg = wl.row_ptr[1:] - wl.row_ptr[:-1]
+    maxdeg = int(deg.max())
+    key = dom * (maxdeg + 1) + (maxdeg - deg)
+    return torch.sort(key, stable=True).indices
+
+
 def block_column_reuse(row_ptr, col_rel, rows_per_block: int = 64, sample_blocks: int = 200_000,
-                       seed: int = 3) -> dict:
+                       seed: int = 3, perm=None) -> dict:
     """What LDS-staged column tiles could save: over a uniform sample of
     blocks of consecutive (relabelled) rows, the share of the blocks'
     nonzeros whose column already occurred in the same block -- the gathers
     a block that stages each distinct row of U once would not repeat -- and
     the share of those repeats that fall on the 32,768 most gathered rows
-    (4 MB at c = 32, what one XCD's L2 holds; hits there already)."""
+    (4 MB at c = 32, what one XCD's L2 holds; hits there already).  The
+    renumbering is the degree order unless perm (new row k is old row
+    perm[k]) is given; "hottest" then means the first 32,768 new rows."""
     import torch
     n = row_ptr.numel() - 1
     deg = (row_ptr[1:] - row_ptr[:-1])
-    perm = torch.sort(-deg, stable=True).indices
+    if perm is None:
+        perm = torch.sort(-deg, stable=True).indices
     rp_rel = torch.zeros(n + 1, dtype=torch.int64, device=row_ptr.device)
     rp_rel[1:] = torch.cumsum(deg[perm], 0)
     nblk = (n + rows_per_block - 1) // rows_per_block
@@ -192,7 +277,30 @@ def gather_ceiling(args, wl, c: int) -> dict:
     rnd = torch.randint(0, n, (wl.nnz,), device="cuda", dtype=torch.int32,
                         generator=torch.Generator(device="cuda").manual_seed(5))
     best(rnd, U32, "uniform_random_fp32")
-    del rnd, col_rel, U32
+    del rnd
+    if getattr(args, "locality_orders", False) and wl.meta.get("pattern") == "chung-lu":
+        # other renumberings of the same matrix, on the same probe
+        del col_rel
+        t0 = time.time()
+        perm, reached = cuthill_mckee_order(wl.row_ptr, wl.col_idx)
+        log(f"gather ceiling: Cuthill-McKee order in {time.time() - t0:.1f} s "
+            f"({reached} rows reached from the highest-degree row)")
+        col_cm, _ = relabelled_columns(wl.row_ptr, wl.col_idx, perm)
+        out["cuthill_mckee_rows_reached"] = reached
+        out["lds_column_tiles_cuthill_mckee"] = block_column_reuse(wl.row_ptr, col_cm, perm=perm)
+        log(f"gather ceiling: Cuthill-McKee columns repeated within 64-row blocks "
+            f"{100 * out['lds_column_tiles_cuthill_mckee']['repeated_columns_share']:.2f} %")
+        del perm
+        best(col_cm, U32, "cuthill_mckee_fp32")
+        del col_cm
+        perm = community_order(wl, args.seed, c)
+        col_co, _ = relabelled_columns(wl.row_ptr, wl.col_idx, perm)
+        del perm
+        best(col_co, U32, "planted_community_fp32")
+        del col_co
+    else:
+        del col_rel
+    del U32
     torch.cuda.empty_cache()
     return out
 
@@ -614,6 +722,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gather-ceiling", action="store_true",
                     help="skip the flat-gather measurement of the product's column sequence")
+    ap.add_argument("--locality-orders", action="store_true",
+                    help="also time the flat gather under a Cuthill-McKee and a planted-community "
+                         "renumbering (about a minute more)")
     ap.add_argument("--cpu-sample-n", type=int, default=1_000_000)
     ap.add_argument("--cpu-iters", type=int, default=8,
                     help="oracle iterations on the power-law sample (median of 2..K)")
