@@ -56,7 +56,10 @@ def single_pass_bytes(n: int, c: int, nnz: int, n_long: int, nnz_long: int) -> d
 
 
 def algorithmic_bytes(n: int, c: int, nnz: int, precision: str) -> dict:
-    """Bytes each launch must move at least (index 4 B, row pointer 8 B)."""
+    """Bytes each launch must move at least (index 4 B, row pointer 8 B), and
+    the iteration's method minimum: one pass that reads S and the rows of Y_n
+    and Xbar_{n-1} once and writes Xbar_n and Y_{n+1} (rows in the master
+    precision)."""
     b_val = {"fp32": 4, "fp64": 8, "mixed": 2}[precision]
     b_u = {"fp32": 4, "fp64": 8, "mixed": 2}[precision]
     b_z = 8 if precision == "fp64" else 4
@@ -65,7 +68,56 @@ def algorithmic_bytes(n: int, c: int, nnz: int, precision: str) -> dict:
     fused = 2 * n * c * b_x + 2 * n * c * b_z + n * c * b_x
     if precision == "mixed":
         fused += n * c * 2
-    return {"spmm": spmm, "fused": fused}
+    minimum = 8 * (n + 1) + nnz * (4 + b_val) + 4 * n * c * b_x
+    return {"spmm": spmm, "fused": fused, "iteration_minimum": minimum}
+
+
+def copy_bandwidth(mib: int = 4096) -> float:
+    """GB/s of a plain elementwise copy of `mib` MiB (read + write counted),
+    the best of five launches on torch's current stream."""
+    import torch
+    x = torch.ones(mib * (1 << 18), device="cuda")
+    y = torch.empty_like(x)
+    torch.mul(x, 1.0, out=y)
+    best = float("inf")
+    for _ in range(5):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        torch.mul(x, 1.0, out=y)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]))
+    gbs = 2 * x.numel() * 4 / (best * 1e6)
+    del x, y
+    torch.cuda.empty_cache()
+    return gbs
+
+
+def backtracking_run(args, wl) -> dict:
+    """FISTA with backtracking on the same instance (L0 = L_thm/100, eta 2):
+    iterations per second and trials per iteration over a short run."""
+    import torch
+    import paper_2506_04045_amd as fc
+    t0 = time.perf_counter()
+    s = fc.Solver(wl.row_ptr, wl.col_idx, wl.val, args.c, wl.U0, precision=args.precision,
+                  accelerate=True, step=0.0, backtrack=True, reorder=args.reorder)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    w = s.step(2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info = s.step(args.backtrack_iters)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    s.close()
+    out = {"iterations": args.backtrack_iters, "seconds": secs,
+           "iters_per_s": args.backtrack_iters / secs,
+           "trials_per_iteration": (info.trials - w.trials) / args.backtrack_iters,
+           "L_last": info.L, "f": info.f, "setup_s": setup,
+           "rule": "Beck-Teboulle backtracking, L0 = L_thm/100, eta 2, loss in the product's epilogue"}
+    log(f"backtracking run: {out['iters_per_s']:.1f} it/s, "
+        f"{out['trials_per_iteration']:.2f} trials per iteration")
+    return out
 
 
 def measured_traffic(kernel: str, workload_key: str):
@@ -722,6 +774,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gather-ceiling", action="store_true",
                     help="skip the flat-gather measurement of the product's column sequence")
+    ap.add_argument("--backtrack-iters", type=int, default=10,
+                    help="iterations of the backtracking run on the same instance (0 disables it)")
     ap.add_argument("--locality-orders", action="store_true",
                     help="also time the flat gather under a Cuthill-McKee and a planted-community "
                          "renumbering (about a minute more)")
@@ -831,18 +885,26 @@ def main() -> int:
     alg = (single_pass_bytes(n, c, nnz, n_long, nnz_long) if single
            else algorithmic_bytes(n, c, nnz, prec))
     kernels = {}
+    wkey = (f"powerlaw_n{n}_c{c}_{prec}_{args.reorder}" + ("_deferred" if defer else "")
+            + ("_single" if single else ""))
+    copy_gbs = copy_bandwidth()
+    log(f"plain copy {copy_gbs:.0f} GB/s")
     for k in ("spmm", "fused"):
         gbs = alg[k] / (avg[k] * 1e-3) / 1e9
         kernels[k] = {"avg_ms": avg[k], "algorithmic_bytes": alg[k], "achieved_GBps": gbs,
                       "frac_of_hbm_peak": gbs / HBM_PEAK_GBS}
+        counted = measured_traffic(k, wkey)
+        if counted:   # HBM bytes from the committed counter summary (same kernel source)
+            kernels[k]["counter_bytes"] = counted
+            kernels[k]["counter_GBps"] = counted / (avg[k] * 1e-3) / 1e9
+            kernels[k]["counter_frac_of_hbm_peak"] = kernels[k]["counter_GBps"] / HBM_PEAK_GBS
+            kernels[k]["counter_frac_of_copy"] = kernels[k]["counter_GBps"] / copy_gbs
     if single:
         kernels["fused"]["kernel"] = "k_single (single-pass iteration, light rows' products included)"
         kernels["spmm"]["kernel"] = f"k_spmm pre-pass over the {n_long:,} rows longer than 64 nonzeros"
     kernels["reduce"] = {"avg_ms": avg["reduce"]}
     kernels["control"] = {"avg_ms": avg["control"]}
     dom = max(("spmm", "fused"), key=lambda k: avg[k])
-    wkey = (f"powerlaw_n{n}_c{c}_{prec}_{args.reorder}" + ("_deferred" if defer else "")
-            + ("_single" if single else ""))
     traffic = measured_traffic(dom, wkey)
     mfma = measured_mfma(wkey)
     if mfma:
@@ -852,12 +914,16 @@ def main() -> int:
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": kernels[dom]["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic}
 
+    roofline["copy_GBps"] = copy_gbs
     ceiling = None
-    if single:
-        it_gbs = alg["iteration_minimum"] / (elapsed / args.steps) / 1e9
-        roofline["iteration_minimum_bytes"] = alg["iteration_minimum"]
-        roofline["iteration_GBps"] = it_gbs
-        roofline["iteration_frac"] = it_gbs / HBM_PEAK_GBS
+    step_s = elapsed / args.steps
+    it_gbs = alg["iteration_minimum"] / step_s / 1e9
+    roofline["iteration_minimum_bytes"] = alg["iteration_minimum"]
+    roofline["iteration_GBps"] = it_gbs
+    roofline["iteration_frac"] = it_gbs / HBM_PEAK_GBS
+    if not single:   # the two passes as built
+        roofline["iteration_as_built_bytes"] = alg["spmm"] + alg["fused"]
+        roofline["iteration_as_built_frac"] = (alg["spmm"] + alg["fused"]) / step_s / 1e9 / HBM_PEAK_GBS
     if not args.no_gather_ceiling and prec == "fp32":
         ceiling = gather_ceiling(args, wl, c)
         roofline["gather_ceiling_ms"] = ceiling["relabelled_fp32_ms"]
@@ -865,6 +931,9 @@ def main() -> int:
         # single-pass kernel's and the pre-pass's together
         gather_ms = avg["spmm"] + (avg["fused"] if single else 0.0)
         roofline["frac_of_gather_ceiling"] = ceiling["relabelled_fp32_ms"] / gather_ms
+    backtracking = None
+    if args.backtrack_iters > 0 and not args.backtrack:
+        backtracking = backtracking_run(args, wl)
     del wl
     torch.cuda.empty_cache()
     serving = None
@@ -917,6 +986,7 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "gather_ceiling": ceiling,
+        "backtracking_run": backtracking,
         "serving": serving,
         "mixed_time_to_target": mixed_target,
         "artificial_two_cluster": artificial,
