@@ -338,6 +338,15 @@ fc_status fc_gather_probe(const int32_t *col_idx, int64_t nnz, const void *U, in
 /* Thread-local message of the last failed call on this thread ("" if none). */
 const char *fc_last_error(void);
 
+/* Test hook for the error paths (callers: tests of out-of-memory handling).
+ * after >= 0: the next `after` device or pinned-host allocations the library
+ * makes (any thread: solvers, stateless calls, the serving worker) succeed
+ * and every later one fails as if the GPU were out of memory, until the hook
+ * is called again; after < 0 turns it off (the default).  The failing call
+ * returns FC_ERR_OUT_OF_MEMORY (a served request gets it as its status) and
+ * frees what it had allocated.  Process-wide; not for production use. */
+void fc_debug_fail_allocations(int64_t after);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of many solves of problem (P) on one GPU.
  *

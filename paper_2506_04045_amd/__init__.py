@@ -19,7 +19,7 @@ import torch
 
 from . import _native as N
 
-__all__ = ["Solver", "Server", "Info", "objective", "project", "spmm", "gram", "gram_noalloc", "gather_probe", "spectral_norm",
+__all__ = ["Solver", "Server", "Info", "objective", "project", "spmm", "gram", "gram_noalloc", "gather_probe", "debug_fail_allocations", "spectral_norm",
            "library_path"]
 
 _PREC = {"fp64": N.FC_PREC_FP64, "fp32": N.FC_PREC_FP32, "mixed": N.FC_PREC_MIXED}
@@ -473,6 +473,13 @@ def gather_probe(col_idx: torch.Tensor, U: torch.Tensor, wg_per_cu: int = 16, re
                                      U.shape[0], row_bytes, wg_per_cu, reps,
                                      _stream_ptr(stream), ctypes.byref(ms)))
     return float(ms.value)
+
+
+def debug_fail_allocations(after: int) -> None:
+    """Test hook (fc_debug_fail_allocations): after `after` more successful
+    library allocations every later one fails as out of memory; a negative
+    value turns the injection off."""
+    N.load().fc_debug_fail_allocations(int(after))
 
 
 def spectral_norm(row_ptr, col_idx, val, diag: str = "unit", max_iter: int = 1000,

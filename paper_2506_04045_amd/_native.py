@@ -33,7 +33,7 @@ EXPORTED = [
     "fc_server_opts_default", "fc_server_clock", "fc_server_create", "fc_server_submit",
     "fc_server_poll", "fc_server_get_u", "fc_server_release", "fc_server_stats",
     "fc_server_destroy", "fc_server_tune", "fc_hessian_vector", "fc_curvature",
-    "fc_gram_noalloc", "fc_gather_probe", "fc_server_cancel",
+    "fc_gram_noalloc", "fc_gather_probe", "fc_server_cancel", "fc_debug_fail_allocations",
 ]
 
 
@@ -136,6 +136,8 @@ def load() -> ctypes.CDLL:
     lib.fc_gram_noalloc.restype = st
     lib.fc_gather_probe.argtypes = [P, i64, P, i64, i32, i32, i32, P, ctypes.POINTER(f64)]
     lib.fc_gather_probe.restype = st
+    lib.fc_debug_fail_allocations.argtypes = [i64]
+    lib.fc_debug_fail_allocations.restype = None
     lib.fc_spectral_norm.argtypes = [ctypes.POINTER(CSR), ctypes.c_int, i32, f64, P,
                                      ctypes.POINTER(f64), ctypes.POINTER(i32)]
     lib.fc_spectral_norm.restype = st

@@ -15,6 +15,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <climits>
 #include <cmath>
@@ -48,11 +49,41 @@ fc_status fail(fc_status s, const std::string &msg) {
     return s;
 }
 
-#define HIPCHK(expr)                                                                   \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(FC_ERR_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+// Allocation-failure injection (fc_debug_fail_allocations): -1 when off;
+// k >= 0 lets k more allocations succeed and fails every later one as out
+// of memory.  Every device and pinned allocation of the library goes
+// through the three functions below.
+std::atomic<int64_t> g_alloc_countdown{-1};
+
+bool injected_alloc_failure() {
+    int64_t v = g_alloc_countdown.load(std::memory_order_relaxed);
+    while (v >= 0) {
+        if (v == 0)
+            return true;
+        if (g_alloc_countdown.compare_exchange_weak(v, v - 1, std::memory_order_relaxed))
+            return false;
+    }
+    return false;
+}
+
+hipError_t lib_malloc(void **p, size_t bytes) {
+    return injected_alloc_failure() ? hipErrorOutOfMemory : hipMalloc(p, bytes);
+}
+
+hipError_t lib_malloc_async(void **p, size_t bytes, hipStream_t s) {
+    return injected_alloc_failure() ? hipErrorOutOfMemory : hipMallocAsync(p, bytes, s);
+}
+
+hipError_t lib_host_malloc(void **p, size_t bytes) {
+    return injected_alloc_failure() ? hipErrorOutOfMemory : hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
+#define HIPCHK(expr)                                                                    \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess)                                                           \
+            return fail(e_ == hipErrorOutOfMemory ? FC_ERR_OUT_OF_MEMORY : FC_ERR_DEVICE, \
+                        std::string(#expr) + ": " + hipGetErrorString(e_));             \
     } while (0)
 
 int cp_of(int c) {
@@ -105,7 +136,7 @@ struct DevBuf {
 
 hipError_t dev_alloc(DevBuf &b, size_t bytes, hipStream_t s) {
     b.s = s;
-    return hipMallocAsync(&b.p, bytes > 0 ? bytes : 16, s);
+    return lib_malloc_async(&b.p, bytes > 0 ? bytes : 16, s);
 }
 
 // Reduction launch: out[e] = sum over np partial rows of in (row stride ld).
@@ -132,7 +163,7 @@ struct HeavyPlan {
     }
     template <typename P> hipError_t alloc(P **p, size_t bytes) {
         void *q = nullptr;
-        hipError_t e = hipMallocAsync(&q, bytes > 0 ? bytes : 16, s);
+        hipError_t e = lib_malloc_async(&q, bytes > 0 ? bytes : 16, s);
         if (e == hipSuccess) {
             bufs.push_back(q);
             *p = (P *)q;
@@ -386,7 +417,7 @@ struct fc_solver {
     template <typename P> hipError_t alloc(P **p, size_t bytes) {
         void *q = nullptr;
         const size_t b = bytes > 0 ? bytes : 16;
-        hipError_t e = pooled ? hipMallocAsync(&q, b, stream) : hipMalloc(&q, b);
+        hipError_t e = pooled ? lib_malloc_async(&q, b, stream) : lib_malloc(&q, b);
         if (e == hipSuccess) {
             allocs.push_back(q);
             bytes_held += b;
@@ -733,6 +764,8 @@ void fc_options_default(fc_options *opt) {
 }
 
 const char *fc_last_error(void) { return g_last_error.c_str(); }
+
+void fc_debug_fail_allocations(int64_t after) { g_alloc_countdown.store(after < 0 ? -1 : after); }
 
 }  // extern "C"
 
