@@ -774,6 +774,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-gather-ceiling", action="store_true",
                     help="skip the flat-gather measurement of the product's column sequence")
+    ap.add_argument("--history-jsonl", default="",
+                    help="write the headline solve's per-iteration records (loss, decrease, step, "
+                         "inertial weight, trials, gradient-mapping norm) to this JSONL file")
     ap.add_argument("--backtrack-iters", type=int, default=10,
                     help="iterations of the backtracking run on the same instance (0 disables it)")
     ap.add_argument("--locality-orders", action="store_true",
@@ -874,6 +877,9 @@ def main() -> int:
     elapsed = time.perf_counter() - t0
     log(f"timed {args.steps} iterations in {elapsed:.3f} s, f={info.f:.6e}")
     hist = solver.history()
+    if args.history_jsonl:
+        log(f"wrote {solver.write_history_jsonl(args.history_jsonl)} iteration records to "
+            f"{args.history_jsonl}")
     f0, f_end = float(hist["f"][0]), float(info.f)
     tau = float(hist["tau"][1])
     trials_per_iter = (info.trials - trials0) / max(1, args.steps)

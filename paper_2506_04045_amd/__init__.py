@@ -19,7 +19,7 @@ import torch
 
 from . import _native as N
 
-__all__ = ["Solver", "Server", "Info", "objective", "project", "spmm", "gram", "gram_noalloc", "gather_probe", "debug_fail_allocations", "spectral_norm",
+__all__ = ["Solver", "Server", "Info", "objective", "project", "spmm", "gram", "gram_noalloc", "gather_probe", "debug_fail_allocations", "history_records", "spectral_norm",
            "library_path"]
 
 _PREC = {"fp64": N.FC_PREC_FP64, "fp32": N.FC_PREC_FP32, "mixed": N.FC_PREC_MIXED}
@@ -114,6 +114,39 @@ def _options(c: int, precision: str = "fp32", diag: str = "unit", accelerate: bo
     return opt
 
 
+def history_records(hist: dict, accelerate: bool = True) -> list:
+    """Per-iteration records of a solver history (Solver.history): for
+    iteration n = 0 (the start) .. K, the loss f(Xbar_n) and its decrease
+    f(Xbar_{n-1}) - f(Xbar_n) (None where a loss was not formed: deferred or
+    single-pass iterations between read-outs), the accepted step tau_n and
+    L_n = 1/tau_n, the trials of the iteration, the gradient-mapping norm
+    r_n, and beta_n, the weight that formed the point the iteration stepped
+    from: Y_n = Xbar_{n-1} + beta_n (Xbar_{n-1} - Xbar_{n-2}) with t_1 = 1,
+    t_{k+1} = (1 + sqrt(1 + 4 t_k^2)) / 2 and beta_n = (t_{n-1} - 1) / t_n
+    (Alg. 4; 0 for n <= 2 and for GPA)."""
+    def num(x):
+        x = float(x)
+        return x if math.isfinite(x) else None
+
+    f, tau, trials, r = hist["f"], hist["tau"], hist["trials"], hist["r"]
+    out = []
+    t_prev, t_cur = 1.0, 1.0   # t_{n-1}, t_n
+    for n in range(len(f)):
+        rec = {"iter": n, "f": num(f[n])}
+        if n == 0:
+            out.append(rec)
+            continue
+        if n >= 2:
+            t_prev, t_cur = t_cur, (1.0 + math.sqrt(1.0 + 4.0 * t_cur * t_cur)) / 2.0
+        beta = (t_prev - 1.0) / t_cur if (accelerate and n >= 2) else 0.0
+        df = (f[n - 1] - f[n]) if (math.isfinite(f[n - 1]) and math.isfinite(f[n])) else math.nan
+        rec.update({"df": num(df), "tau": num(tau[n]),
+                    "L": num(1.0 / tau[n]) if tau[n] > 0 else None,
+                    "beta": beta, "trials": int(trials[n]), "pgrad": num(r[n])})
+        out.append(rec)
+    return out
+
+
 class Solver:
     """One solve of problem (P): fc_create / fc_step / fc_solve / fc_get_u."""
 
@@ -128,6 +161,7 @@ class Solver:
         self._csr = _CsrView(row_ptr, col_idx, val)
         self.n, self.c = self._csr.n, int(c)
         self.precision = precision
+        self.accelerate = bool(accelerate)
         opt = _options(c, precision, diag, accelerate, step, backtrack, L0, eta, max_iter,
                        check_every, tol_loss, tol_pgrad, validate, norm_estimate, reorder,
                        defer_loss, single_pass)
@@ -193,6 +227,16 @@ class Solver:
                                         trials.ctypes.data, r.ctypes.data, ctypes.byref(cnt)))
         k = cnt.value
         return dict(f=f[:k].copy(), tau=tau[:k].copy(), trials=trials[:k].copy(), r=r[:k].copy())
+
+    def write_history_jsonl(self, path: str, cap: int | None = None) -> int:
+        """One JSON record per iteration (history_records) written to `path`;
+        returns the number of records."""
+        import json
+        recs = history_records(self.history(cap), self.accelerate)
+        with open(path, "w") as fh:
+            for r in recs:
+                fh.write(json.dumps(r) + "\n")
+        return len(recs)
 
     def get_state(self) -> bytes:
         """Checkpoint (fc_get_state) as a bytes object."""

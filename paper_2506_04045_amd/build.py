@@ -22,6 +22,8 @@ HIPCC_FLAGS = [
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),
+    # named host ranges for timeline tools (rocprofv3 --marker-trace)
+    "-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib",
 ]
 
 

@@ -32,6 +32,7 @@
 
 #include <hipcub/device/device_radix_sort.hpp>
 #include <hipcub/device/device_scan.hpp>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include "fc.h"
 #include "fc_host.hpp"
@@ -48,6 +49,17 @@ fc_status fail(fc_status s, const std::string &msg) {
     g_last_error = msg;
     return s;
 }
+
+// Named host ranges for timeline tools (rocprofv3 --marker-trace): the
+// set-up, each fc_step / fc_solve call, each group of trials between two
+// state readbacks, the loss read-out, the stateless calls and the serving
+// worker's phases.  Without a tool attached a range costs two calls.
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 // Allocation-failure injection (fc_debug_fail_allocations): -1 when off;
 // k >= 0 lets k more allocations succeed and fails every later one as out
@@ -639,7 +651,7 @@ void fill_info(const fc_solver *h, fc_info *info) {
     info->f_prev = h->h.f_prev;
     info->L = h->h.iter > 0 || h->backtrack ? h->h.L : 1.0 / h->h.tau;
     info->t = h->h.t;
-    info->beta = h->h.beta_next;
+    info->beta = h->h.beta;   // the weight that forms Y_{iter+1}
     info->pgrad = h->h.r;
     info->pgrad_rel = h->h.r1 > 0.0 ? h->h.r / h->h.r1 : 0.0;
 }
@@ -706,6 +718,7 @@ fc_status run_until(fc_solver *h, int32_t target, int32_t max_iter, EventLog *lo
     if (st != FC_OK)
         return st;
     while (h->h.active) {
+        TraceRange trace_range("trials and state readback");
         int launches = h->backtrack ? h->check_every : (target - h->h.iter);
         if (launches < 1)
             launches = 1;
@@ -725,6 +738,7 @@ fc_status run_until(fc_solver *h, int32_t target, int32_t max_iter, EventLog *lo
         HIPCHK(log->collect());
     if ((h->defer || h->single) && !h->h.f_known && h->h.error == ERR_NONE) {
         // the loss of the last accepted iterate
+        TraceRange trace_range("loss read-out");
         st = launch_eval(h);
         if (st == FC_OK)
             st = read_state(h);
@@ -1215,11 +1229,13 @@ extern "C" {
 fc_status fc_create(const fc_csr *S, const fc_options *opt, const void *U0, fc_dtype u0_dtype,
                     void *stream, fc_solver **out) {
     g_last_error.clear();
+    TraceRange trace_range("fc_create");
     return create_impl(S, opt, U0, u0_dtype, (hipStream_t)stream, 65536, false, out);
 }
 
 fc_status fc_step(fc_solver *h, int32_t iters, fc_info *info) {
     g_last_error.clear();
+    TraceRange trace_range("fc_step");
     if (!h)
         return fail(FC_ERR_INVALID_ARG, "solver is NULL");
     if (iters < 0)
@@ -1235,6 +1251,7 @@ fc_status fc_step(fc_solver *h, int32_t iters, fc_info *info) {
 
 fc_status fc_step_profiled(fc_solver *h, int32_t iters, fc_info *info, fc_kernel_times *times) {
     g_last_error.clear();
+    TraceRange trace_range("fc_step_profiled");
     if (!h || !times)
         return fail(FC_ERR_INVALID_ARG, "solver or times is NULL");
     if (iters < 0)
@@ -1254,6 +1271,7 @@ fc_status fc_step_profiled(fc_solver *h, int32_t iters, fc_info *info, fc_kernel
 
 fc_status fc_solve(fc_solver *h, fc_info *info) {
     g_last_error.clear();
+    TraceRange trace_range("fc_solve");
     if (!h)
         return fail(FC_ERR_INVALID_ARG, "solver is NULL");
     fc_status st = FC_OK;
@@ -1551,6 +1569,7 @@ extern "C" {
 fc_status fc_spmm(const fc_csr *S, fc_diag diag, const void *U, void *Z, fc_dtype dtype, int32_t c,
                   void *stream) {
     g_last_error.clear();
+    TraceRange trace_range("fc_spmm");
     fc_status st = check_csr_args(S);
     if (st != FC_OK)
         return st;
@@ -1607,6 +1626,7 @@ fc_status fc_spmm(const fc_csr *S, fc_diag diag, const void *U, void *Z, fc_dtyp
 fc_status fc_objective(const fc_csr *S, fc_diag diag, const void *U, fc_dtype u_dtype, int32_t c,
                        void *stream, double *f_out) {
     g_last_error.clear();
+    TraceRange trace_range("fc_objective");
     fc_status st = check_csr_args(S);
     if (st != FC_OK)
         return st;
@@ -1663,6 +1683,7 @@ fc_status fc_objective(const fc_csr *S, fc_diag diag, const void *U, fc_dtype u_
 
 fc_status fc_gram(const void *U, fc_dtype dtype, int64_t n, int32_t c, void *stream, double *G_out) {
     g_last_error.clear();
+    TraceRange trace_range("fc_gram");
     if (!U || !G_out)
         return fail(FC_ERR_INVALID_ARG, "U or G_out is NULL");
     if (n < 1 || c < 1 || c > 64)

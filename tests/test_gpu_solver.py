@@ -226,6 +226,29 @@ def test_solve_budget_and_info(fc):
         assert more.t == pytest.approx(t[15], rel=1e-14)
 
 
+@pytest.mark.parametrize("backtrack", [False, True])
+def test_history_records_match_the_device_state(fc, tmp_path, backtrack):
+    """The JSONL log's inertial weight for iteration K is the weight the
+    device reported, after K - 1 iterations, for forming Y_K; its steps and
+    losses are the history's."""
+    wl = W.er_planted(3000, 8, 10.0, 0.05, 9)
+    S = wl.to("cuda")
+    kw = dict(backtrack=True) if backtrack else dict(step=1e-3)
+    with fc.Solver(S.row_ptr, S.col_idx, S.val, 8, S.U0, **kw) as s:
+        betas = []
+        for _ in range(12):
+            betas.append(s.info().beta)
+            s.step(1)
+        path = tmp_path / "hist.jsonl"
+        assert s.write_history_jsonl(str(path)) == 13
+        hist = s.history()
+    recs = [json.loads(line) for line in path.read_text().splitlines()]
+    for k in range(1, 13):
+        assert recs[k]["beta"] == pytest.approx(betas[k - 1], rel=1e-14, abs=1e-300)
+        assert recs[k]["tau"] == hist["tau"][k] and recs[k]["f"] == hist["f"][k]
+        assert recs[k]["trials"] == hist["trials"][k]
+
+
 def test_single_row_and_single_cluster(fc):
     rp = np.array([0, 0], dtype=np.int64)
     ci = np.zeros(0, dtype=np.int32)
