@@ -1818,11 +1818,46 @@ __device__ __forceinline__ double block_sum_256(double v) {
     return r;
 }
 
+// K such sums at once, each in exactly the order of block_sum_256 (so each
+// result has the same bits), with one pair of barriers for all of them.
+template <int K>
+__device__ __forceinline__ void block_sums_256(double (&v)[K]) {
+    __shared__ double wsum[K][4];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            v[k] += shfl_xor_d(v[k], off);
+    if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            wsum[k][wave] = v[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+        v[k] = ((wsum[k][0] + wsum[k][1]) + wsum[k][2]) + wsum[k][3];
+    __syncthreads();
+}
+
+// The device state as 8-byte words (copies between HBM and LDS).
+typedef uint64_t __attribute__((__may_alias__)) state_word;
+constexpr int STATE_WORDS = (int)(sizeof(DevState) / sizeof(uint64_t));
+static_assert(sizeof(DevState) % sizeof(uint64_t) == 0 && STATE_WORDS <= 256,
+              "the state is copied one 8-byte word per thread");
+
+// The controller is one workgroup and latency-bound: its inputs (the state,
+// the reduced matrices, the partial sums) are loaded by all threads at
+// once, the state is worked on in LDS by one thread and written back by all
+// threads, and the four sums are reduced together.  Every value is formed
+// exactly as it would be one load after the other.
 template <typename T, int CPM>
 __device__ __forceinline__ void control_body(const Inst &I, int mode) {
     using L = FusedLayout<CPM>;
+    constexpr int PER = (CPM * CPM + 255) / 256;   // matrix entries per thread
     __shared__ int decision;
-    DevState *__restrict__ st = I.st;
+    __shared__ DevState st_lds;
+    DevState *__restrict__ gst = I.st;
     const double *__restrict__ red_mats = I.red_mats;
     double *__restrict__ GY64 = I.GY64;
     T *__restrict__ GYs = (T *)I.GYs;
@@ -1835,8 +1870,12 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
     // mode 0: initial evaluation; 1: after a trial; 2: deferred evaluation of
     // the current iterate after the trials (nothing else changes); 3: the
     // read-out loss of a single-pass instance (nothing else changes)
-    if (mode == 1 && !st->active)
+    if (mode == 1 && !gst->active)
         return;
+    if (tid < STATE_WORDS)
+        reinterpret_cast<state_word *>(&st_lds)[tid] = reinterpret_cast<const state_word *>(gst)[tid];
+    DevState *__restrict__ st = &st_lds;   // valid after the barrier of the sums below
+    const int c = gst->c, accelerate = gst->accelerate, backtrack = gst->backtrack;
     // a single-pass iteration forms no loss terms; its pass leaves the Gram
     // matrix of the next extrapolated point in the second matrix slot
     const bool single = I.pass_kind == PASS_SINGLE;
@@ -1844,30 +1883,42 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
     // the products' terms sum_i <x_i, (S X)_i>: workgroup partials of the
     // sparse product, combined in a fixed order (a deferred instance forms
     // them in the fused pass instead; its products write no partials)
-    double tr_total = 0.0;
-    if (!I.defer && !single_step) {
+    const bool want_tr = !I.defer && !single_step;
+    double sums[4] = {0.0, 0.0, 0.0, 0.0};   // trace terms, ||G_p||^2, <M, G_p + G_Y>, G_next sum
+    if (want_tr) {
         const int64_t np = (int64_t)I.g_spmm + I.g_comb;
-        double a = 0.0;
 #pragma unroll 8
         for (int64_t q = tid; q < np; q += 256)   // loads run ahead, adds stay in order
-            a += I.part_spmm[q];
-        tr_total = block_sum_256(a);
+            sums[0] += I.part_spmm[q];
     }
-    const int c = st->c;
     const double *Gp = red_mats + (single_step ? L::MAT : 0);   // Gram of the new point
-    const double *Gnext = single ? Gp : red_mats + (mode == 1 && st->accelerate ? L::MAT : 0);
+    const double *Gnext = single ? Gp : red_mats + (mode == 1 && accelerate ? L::MAT : 0);
     const double *Mx = red_mats + 2 * L::MAT;
     const double *sc = red_mats + 3 * L::MAT;
 
-    // ||G_p||^2 and (backtracking) <M, G_p + G_Y>, fixed-order tree sums
-    double a_sq = 0.0, a_m = 0.0;
-    for (int e = tid; e < CPM * CPM; e += 256) {
-        a_sq += Gp[e] * Gp[e];
-        if (mode == 1 && st->backtrack)
-            a_m += Mx[e] * (Gp[e] + GY64[e]);
+    // ||G_p||^2, (backtracking) <M, G_p + G_Y>, and the sum over the c x c
+    // block of the next extrapolated point's Gram matrix (kept in registers
+    // for the copy below), fixed-order tree sums
+    const bool want_m = mode == 1 && backtrack;
+    double gnext[PER];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + 256 * k;
+        gnext[k] = 0.0;
+        if (e < CPM * CPM) {
+            sums[1] += Gp[e] * Gp[e];
+            if (want_m)
+                sums[2] += Mx[e] * (Gp[e] + GY64[e]);
+            gnext[k] = Gnext[e];
+            if (e / CPM < c && e % CPM < c)
+                sums[3] += gnext[k];
+        }
     }
-    const double gp_sq = block_sum_256(a_sq);
-    const double m_dot = mode == 1 && st->backtrack ? block_sum_256(a_m) : 0.0;
+    block_sums_256(sums);
+    const double tr_total = want_tr ? sums[0] : 0.0;
+    const double gp_sq = sums[1];
+    const double m_dot = want_m ? sums[2] : 0.0;
+    const double mu_next = sums[3] / ((double)c * (double)c);
 
     if (tid == 0) {
         // deferred: the products carry no terms; the fused kernel (or the
@@ -2028,28 +2079,28 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
                 accept = 0;
             }
         }
+        if (accept)
+            st->mu = mu_next;
         decision = accept;
     }
     __syncthreads();
-    if (!decision)
+    if (tid < STATE_WORDS)
+        reinterpret_cast<state_word *>(gst)[tid] = reinterpret_cast<const state_word *>(&st_lds)[tid];
+    if (!decision) {
+        __syncthreads();   // st_lds is reused by the next call
         return;
+    }
     // G of the next extrapolated point: keep it in double and hand the fused
     // kernel a copy with its mean over the c x c block removed.
-    double msum = 0.0;
-    for (int e = tid; e < CPM * CPM; e += 256) {
-        const int i = e / CPM, j = e % CPM;
-        if (i < c && j < c)
-            msum += Gnext[e];
+#pragma unroll
+    for (int k = 0; k < PER; ++k) {
+        const int e = tid + 256 * k;
+        if (e < CPM * CPM) {
+            const int i = e / CPM, j = e % CPM;
+            GY64[e] = gnext[k];
+            GYs[e] = (i < c && j < c) ? (T)(gnext[k] - mu_next) : (T)0;
+        }
     }
-    const double mu = block_sum_256(msum) / ((double)c * (double)c);
-    for (int e = tid; e < CPM * CPM; e += 256) {
-        const int i = e / CPM, j = e % CPM;
-        const double gv = Gnext[e];
-        GY64[e] = gv;
-        GYs[e] = (i < c && j < c) ? (T)(gv - mu) : (T)0;
-    }
-    if (tid == 0)
-        st->mu = mu;
     __syncthreads();
 }
 
