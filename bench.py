@@ -93,6 +93,50 @@ def copy_bandwidth(mib: int = 4096) -> float:
     return gbs
 
 
+def single_pass_run(args, wl, steps: int) -> dict:
+    """The single-pass iteration (fc_options.single_pass) on the same instance,
+    timed as the headline is (one fc_step call of `steps` iterations after the
+    warm-up, the loss read-out at its end included): iterations per second and
+    its kernels."""
+    import torch
+    import paper_2506_04045_amd as fc
+    t0 = time.perf_counter()
+    s = fc.Solver(wl.row_ptr, wl.col_idx, wl.val, args.c, wl.U0, precision="fp32", accelerate=True,
+                  step=0.0, reorder=args.reorder, single_pass=True)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    info, kt = s.step_profiled(steps)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    s.close()
+    launches = max(1, kt["launches"])
+    deg = wl.row_ptr[1:] - wl.row_ptr[:-1]
+    long_rows = deg > 64
+    n_long, nnz_long = int(long_rows.sum()), int(deg[long_rows].sum())
+    del deg, long_rows
+    alg = single_pass_bytes(wl.n, args.c, wl.nnz, n_long, nnz_long)
+    single_ms = kt["fused_ms"] / launches
+    out = {"iterations": steps, "seconds": secs, "iters_per_s": steps / secs,
+           "ms_per_step": 1e3 * secs / steps, "f": info.f, "setup_s": setup,
+           "k_single_ms": single_ms, "prepass_ms": kt["spmm_ms"] / launches,
+           "reduce_ms": kt["reduce_ms"] / launches, "control_ms": kt["control_ms"] / launches,
+           "k_single_algorithmic_bytes": alg["fused"],
+           "k_single_GBps": alg["fused"] / (single_ms * 1e-3) / 1e9,
+           "iteration_minimum_bytes": alg["iteration_minimum"],
+           "iteration_frac_of_hbm_peak": alg["iteration_minimum"] / (secs / steps) / 1e9 / HBM_PEAK_GBS,
+           "rows_longer_than_64": n_long, "their_nonzeros": nnz_long,
+           "what": ("S applied once per iteration to the stored extrapolated point: a pre-pass "
+                    "over the rows longer than 64 nonzeros, then one kernel that gathers the other "
+                    "rows' products and forms the step, projection, next extrapolated point and "
+                    "Gram; the loss formed once, at the read-out after the timed iterations")}
+    log(f"single-pass run: {out['iters_per_s']:.2f} it/s (k_single {single_ms:.2f} ms, pre-pass "
+        f"{out['prepass_ms']:.2f} ms per iteration)")
+    return out
+
+
 def backtracking_run(args, wl) -> dict:
     """FISTA with backtracking on the same instance (L0 = L_thm/100, eta 2):
     iterations per second and trials per iteration over a short run."""
@@ -777,6 +821,8 @@ def main() -> int:
     ap.add_argument("--history-jsonl", default="",
                     help="write the headline solve's per-iteration records (loss, decrease, step, "
                          "inertial weight, trials, gradient-mapping norm) to this JSONL file")
+    ap.add_argument("--single-pass-leg", type=int, default=1,
+                    help="1: also time the single-pass iteration on the same instance")
     ap.add_argument("--backtrack-iters", type=int, default=10,
                     help="iterations of the backtracking run on the same instance (0 disables it)")
     ap.add_argument("--locality-orders", action="store_true",
@@ -940,6 +986,9 @@ def main() -> int:
     backtracking = None
     if args.backtrack_iters > 0 and not args.backtrack:
         backtracking = backtracking_run(args, wl)
+    single_leg = None
+    if args.single_pass_leg and not single and not args.backtrack and prec == "fp32":
+        single_leg = single_pass_run(args, wl, args.steps)
     del wl
     torch.cuda.empty_cache()
     serving = None
@@ -993,6 +1042,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "gather_ceiling": ceiling,
         "backtracking_run": backtracking,
+        "single_pass_run": single_leg,
         "serving": serving,
         "mixed_time_to_target": mixed_target,
         "artificial_two_cluster": artificial,

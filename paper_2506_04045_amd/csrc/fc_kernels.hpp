@@ -1481,7 +1481,14 @@ __device__ __forceinline__ void single_body(const Inst &I, int64_t blk, int64_t 
     constexpr int BPW = (NSYM + 3) / 4;
     using A4 = typename Acc4<T>::type;
     using L = FusedLayout<CPM>;
-    using Lc = typename SpmmCfg<T, CP>::Light;
+    // light-row teams: where a row takes fewer than four 16-byte lanes the
+    // slots of a team sit side by side on one row and each team has one row
+    // of the tile; wider rows get one-slot teams that walk RPT consecutive
+    // rows, whose row pointers they load together (the tile's gathers wait
+    // on fewer dependent loads than with two-slot teams walking more rows)
+    constexpr int GS1 = TeamCfg<T, CP, 1>::GS;
+    using Lc = TeamCfg<T, CP, (GS1 < 4 ? 4 / GS1 : 1)>;
+    constexpr int RPT = Lc::TEAMS >= 64 ? 1 : 64 / Lc::TEAMS;
     constexpr int NE = Lc::LANE_ELEMS;
     constexpr int DEPTH = 4;
     static_assert(64 % Lc::TEAMS == 0 || Lc::TEAMS >= 64, "every wave walks the same rows");
@@ -1571,30 +1578,38 @@ __device__ __forceinline__ void single_body(const Inst &I, int64_t blk, int64_t 
         {
             const int team = tid / Lc::TEAM, lt = tid % Lc::TEAM;
             const int slot = lt / Lc::GS, sub = lt % Lc::GS;
-            for (int rr = team; rr < 64; rr += Lc::TEAMS) {
-                const int64_t row = wt * 64 + rr;
-                T acc[NE];
+            if (team * RPT < 64) {   // teams past the tile's 64 rows idle
+                const int64_t r0 = wt * 64 + team * RPT;
+                int64_t rp[RPT + 1];
 #pragma unroll
-                for (int q = 0; q < NE; ++q)
-                    acc[q] = (T)0;
-                bool longrow = false;
-                if (row < n) {
-                    const int64_t beg = row_ptr[row], end = row_ptr[row + 1];
-                    if (end - beg > light_max)
-                        longrow = true;
-                    else
-                        team_row_sum<T, T, CP, Lc::SLOTS, DEPTH>(col, val, Y, beg, end, slot, sub, acc,
-                                                                 I.nt_from);
-                }
-                team_slot_sum<Lc::GS, Lc::TEAM>(acc);
-                if (slot == 0) {
-                    if (longrow)
+                for (int k = 0; k <= RPT; ++k)
+                    rp[k] = row_ptr[r0 + k < n ? r0 + k : n];
 #pragma unroll
-                        for (int q = 0; q < NE; ++q)
-                            acc[q] = Zl[row * CP + sub * NE + q];
+                for (int k = 0; k < RPT; ++k) {
+                    const int rr = team * RPT + k;
+                    const int64_t row = r0 + k;
+                    T acc[NE];
 #pragma unroll
                     for (int q = 0; q < NE; ++q)
-                        lds[0][rr * STRIDE + sub * NE + q] = acc[q];
+                        acc[q] = (T)0;
+                    bool longrow = false;
+                    if (row < n) {
+                        if (rp[k + 1] - rp[k] > light_max)
+                            longrow = true;
+                        else
+                            team_row_sum<T, T, CP, Lc::SLOTS, DEPTH>(col, val, Y, rp[k], rp[k + 1], slot,
+                                                                     sub, acc, I.nt_from);
+                    }
+                    team_slot_sum<Lc::GS, Lc::TEAM>(acc);
+                    if (slot == 0) {
+                        if (longrow)
+#pragma unroll
+                            for (int q = 0; q < NE; ++q)
+                                acc[q] = Zl[row * CP + sub * NE + q];
+#pragma unroll
+                        for (int q = 0; q < NE; ++q)
+                            lds[0][rr * STRIDE + sub * NE + q] = acc[q];
+                    }
                 }
             }
         }
@@ -1936,6 +1951,14 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
             st->gsq_c = gp_sq;
             if (hist_f)
                 hist_f[0] = f_p;
+            // the start has no step, trial or gradient mapping: zeros, so
+            // that a checkpoint holds no unwritten memory
+            if (hist_tau)
+                hist_tau[0] = 0.0;
+            if (hist_r)
+                hist_r[0] = 0.0;
+            if (hist_trials)
+                hist_trials[0] = 0;
             if (!(f_p == f_p) || f_p - f_p != 0.0) {
                 st->error = ERR_NONFINITE;
                 st->stop_reason = STOP_ERROR;

@@ -1002,6 +1002,14 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
             h->alloc(&h->shadow[k], (size_t)h->n * h->cp * 2) != hipSuccess)
             return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "bfloat16 shadow buffers"));
     }
+    // the ring slots the set-up does not write start as zeros (a checkpoint
+    // taken before they are first written then holds no unwritten memory)
+    for (int k = 1; k < 3; ++k) {
+        if (hipMemsetAsync(h->X[k], 0, mat_bytes, s) != hipSuccess ||
+            (h->Z[k] != h->Z[0] && hipMemsetAsync(h->Z[k], 0, mat_bytes, s) != hipSuccess) ||
+            (h->shadow[k] && hipMemsetAsync(h->shadow[k], 0, (size_t)h->n * h->cp * 2, s) != hipSuccess))
+            return cleanup(fail(FC_ERR_DEVICE, "clearing the iterate buffers"));
+    }
     if (opt->reorder == FC_REORDER_DEGREE) {
         const fc_dtype vout = h->prec == FC_PREC_MIXED ? FC_F16 : S->values_dtype;
         st = build_degree_order(h, S, vout, s);

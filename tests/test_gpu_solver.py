@@ -350,6 +350,30 @@ def test_checkpoint_resume_is_bitwise(fc, backtrack):
             d.set_state(state)
 
 
+@pytest.mark.parametrize("kw", [dict(step=1e-3), dict(backtrack=True), dict(defer_loss=True, step=1e-3),
+                                dict(single_pass=True, step=1e-3), dict(precision="mixed", step=1e-3)],
+                         ids=["fixed", "backtracking", "deferred", "single_pass", "mixed"])
+def test_checkpoint_bytes_depend_only_on_the_inputs(fc, kw):
+    """Two solvers of the same instance, on buffers that held other data
+    before, give byte-identical checkpoints: at the start (slots not yet
+    written) and after some iterations (padded columns: c = 3, or 6 in mixed
+    precision)."""
+    c = 6 if kw.get("precision") == "mixed" else 3   # mixed precision needs c >= 5
+    wl = W.chung_lu_planted(3000, c, 15.0, 2.1, 2_000.0, 0.05, 17).to("cuda")
+    junk = torch.full((1 << 22,), float("nan"), device="cuda")   # recycled memory
+    del junk
+    states = []
+    for _ in range(2):
+        with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, c, wl.U0, reorder="degree", **kw) as s:
+            first = s.get_state()
+            s.step(6)
+            states.append((first, s.get_state()))
+        filler = torch.randn(1 << 22, device="cuda")   # the next solver reuses dirty memory
+        del filler
+    assert states[0][0] == states[1][0]
+    assert states[0][1] == states[1][1]
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_power_law_instance_follows_the_oracle(fc, prec):
     wl = W.chung_lu_planted(20000, 16, 20.0, 2.1, 50_000.0, 0.05, 5,
