@@ -5,9 +5,16 @@ Default workload: n = 70,000,000 articles, c = 32 clusters, power-law
 similarity (Chung-Lu pattern, degree exponent 2.1, mean degree 20, max
 50,000, ~1.4e9 stored nonzeros), planted overlapping communities with
 noise sigma 0.05, FP32 values and iterates, unit diagonal, FISTA with the
-constant step 1/L of Theorem 3.1.  One step = one iteration: the fused
-extrapolation/gradient/projection/Gram kernel, the sparse product of the new
-iterate with the loss terms, the reductions and the controller.
+constant step 1/L of Theorem 3.1.  One step = one iteration.  By default
+the single-pass iteration: the sparse product of the rows longer than 64
+nonzeros (pre-pass), then one kernel that gathers the other rows' products of
+the extrapolated point and forms the gradient, step, projection, next
+extrapolated point and Gram matrix, then the reduction and the controller;
+the loss of the last iterate is formed at the read-out that ends the timed
+call.  --single-pass 0: the two-pass iteration (the fused step kernel, the
+sparse product of the new iterate, the loss of each iterate formed during
+the next pass).  The other mode is timed beside the headline on the same
+instance.
 
 Prints one JSON line (progress goes to stderr).  Inputs are generated on the
 GPU and resident in HBM before the timed region starts.
@@ -93,16 +100,17 @@ def copy_bandwidth(mib: int = 4096) -> float:
     return gbs
 
 
-def single_pass_run(args, wl, steps: int) -> dict:
-    """The single-pass iteration (fc_options.single_pass) on the same instance,
-    timed as the headline is (one fc_step call of `steps` iterations after the
-    warm-up, the loss read-out at its end included): iterations per second and
-    its kernels."""
+def other_mode_run(args, wl, steps: int, single: bool) -> dict:
+    """The iteration in the mode the headline does not use, on the same
+    instance and timed the same way (one fc_step call of `steps` iterations
+    after the warm-up, its final loss evaluation included): the single-pass
+    iteration, or the two-pass iteration with deferred loss evaluation.
+    Iterations per second and its kernels."""
     import torch
     import paper_2506_04045_amd as fc
     t0 = time.perf_counter()
     s = fc.Solver(wl.row_ptr, wl.col_idx, wl.val, args.c, wl.U0, precision="fp32", accelerate=True,
-                  step=0.0, reorder=args.reorder, single_pass=True)
+                  step=0.0, reorder=args.reorder, single_pass=single, defer_loss=not single)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     s.step(args.warmup)
@@ -117,23 +125,39 @@ def single_pass_run(args, wl, steps: int) -> dict:
     long_rows = deg > 64
     n_long, nnz_long = int(long_rows.sum()), int(deg[long_rows].sum())
     del deg, long_rows
-    alg = single_pass_bytes(wl.n, args.c, wl.nnz, n_long, nnz_long)
-    single_ms = kt["fused_ms"] / launches
     out = {"iterations": steps, "seconds": secs, "iters_per_s": steps / secs,
            "ms_per_step": 1e3 * secs / steps, "f": info.f, "setup_s": setup,
-           "k_single_ms": single_ms, "prepass_ms": kt["spmm_ms"] / launches,
-           "reduce_ms": kt["reduce_ms"] / launches, "control_ms": kt["control_ms"] / launches,
-           "k_single_algorithmic_bytes": alg["fused"],
-           "k_single_GBps": alg["fused"] / (single_ms * 1e-3) / 1e9,
-           "iteration_minimum_bytes": alg["iteration_minimum"],
-           "iteration_frac_of_hbm_peak": alg["iteration_minimum"] / (secs / steps) / 1e9 / HBM_PEAK_GBS,
-           "rows_longer_than_64": n_long, "their_nonzeros": nnz_long,
-           "what": ("S applied once per iteration to the stored extrapolated point: a pre-pass "
-                    "over the rows longer than 64 nonzeros, then one kernel that gathers the other "
-                    "rows' products and forms the step, projection, next extrapolated point and "
-                    "Gram; the loss formed once, at the read-out after the timed iterations")}
-    log(f"single-pass run: {out['iters_per_s']:.2f} it/s (k_single {single_ms:.2f} ms, pre-pass "
-        f"{out['prepass_ms']:.2f} ms per iteration)")
+           "reduce_ms": kt["reduce_ms"] / launches, "control_ms": kt["control_ms"] / launches}
+    if single:
+        alg = single_pass_bytes(wl.n, args.c, wl.nnz, n_long, nnz_long)
+        single_ms = kt["fused_ms"] / launches
+        out.update({"k_single_ms": single_ms, "prepass_ms": kt["spmm_ms"] / launches,
+                    "k_single_algorithmic_bytes": alg["fused"],
+                    "k_single_GBps": alg["fused"] / (single_ms * 1e-3) / 1e9,
+                    "rows_longer_than_64": n_long, "their_nonzeros": nnz_long,
+                    "what": ("single-pass iteration: S applied once per iteration to the stored "
+                             "extrapolated point (a pre-pass over the rows longer than 64 "
+                             "nonzeros, then one kernel that gathers the other rows' products and "
+                             "forms step, projection, next extrapolated point and Gram); the loss "
+                             "formed at the read-out after the timed iterations")})
+        log(f"single-pass run: {out['iters_per_s']:.2f} it/s (k_single {single_ms:.2f} ms, pre-pass "
+            f"{out['prepass_ms']:.2f} ms per iteration)")
+    else:
+        alg = algorithmic_bytes(wl.n, args.c, wl.nnz, "fp32")
+        spmm_ms, fused_ms = kt["spmm_ms"] / launches, kt["fused_ms"] / launches
+        out.update({"spmm_ms": spmm_ms, "fused_ms": fused_ms,
+                    "spmm_algorithmic_bytes": alg["spmm"], "fused_algorithmic_bytes": alg["fused"],
+                    "spmm_GBps": alg["spmm"] / (spmm_ms * 1e-3) / 1e9,
+                    "fused_GBps": alg["fused"] / (fused_ms * 1e-3) / 1e9,
+                    "spmm_frac_of_hbm_peak": alg["spmm"] / (spmm_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "fused_frac_of_hbm_peak": alg["fused"] / (fused_ms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                    "what": ("two-pass iteration: the fused step kernel, then the sparse product "
+                             "of the new iterate (the loss of each iterate formed during the next "
+                             "pass from the rows and products it reads)")})
+        log(f"two-pass run: {out['iters_per_s']:.2f} it/s (sparse product {spmm_ms:.2f} ms, fused "
+            f"{fused_ms:.2f} ms per iteration)")
+    out["iteration_minimum_bytes"] = alg["iteration_minimum"]
+    out["iteration_frac_of_hbm_peak"] = alg["iteration_minimum"] / (secs / steps) / 1e9 / HBM_PEAK_GBS
     return out
 
 
@@ -806,8 +830,10 @@ def main() -> int:
                     help="Beck-Teboulle backtracking (L0 = L_thm/100) instead of the constant step")
     ap.add_argument("--defer-loss", type=int, default=1,
                     help="1: each iterate's loss is formed during the next pass (fc_options.defer_loss)")
-    ap.add_argument("--single-pass", type=int, default=0,
-                    help="1: the single-pass iteration (fc_options.single_pass; FP32, fixed step)")
+    ap.add_argument("--single-pass", type=int, default=1,
+                    help="1 (default): the single-pass iteration (fc_options.single_pass; FP32, "
+                         "fixed step, the loss formed at the read-out); 0: the two-pass iteration "
+                         "with deferred loss evaluation")
     ap.add_argument("--no-smaller", action="store_true",
                     help="skip the n = 2,000 FP64 and n = 1e6 backtracking runs")
     ap.add_argument("--no-artificial", action="store_true",
@@ -821,8 +847,9 @@ def main() -> int:
     ap.add_argument("--history-jsonl", default="",
                     help="write the headline solve's per-iteration records (loss, decrease, step, "
                          "inertial weight, trials, gradient-mapping norm) to this JSONL file")
-    ap.add_argument("--single-pass-leg", type=int, default=1,
-                    help="1: also time the single-pass iteration on the same instance")
+    ap.add_argument("--other-mode-leg", type=int, default=1,
+                    help="1: also time the iteration in the other mode (two-pass or single-pass) "
+                         "on the same instance")
     ap.add_argument("--backtrack-iters", type=int, default=10,
                     help="iterations of the backtracking run on the same instance (0 disables it)")
     ap.add_argument("--locality-orders", action="store_true",
@@ -962,7 +989,9 @@ def main() -> int:
     if mfma:
         for k, v in mfma.items():
             kernels.setdefault(k, {})["mfma"] = v
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": kernels[dom]["achieved_GBps"],
+    names = ({"fused": "k_single_1 (the single-pass kernel)", "spmm": "k_spmm_1 (pre-pass, long rows)"}
+             if single else {"fused": "k_fused_1 (fused step)", "spmm": "k_spmm_1 (sparse product)"})
+    roofline = {"bound": "hbm", "kernel": names[dom], "achieved": kernels[dom]["achieved_GBps"],
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": kernels[dom]["achieved_GBps"] / HBM_PEAK_GBS, "traffic": traffic}
 
@@ -986,9 +1015,14 @@ def main() -> int:
     backtracking = None
     if args.backtrack_iters > 0 and not args.backtrack:
         backtracking = backtracking_run(args, wl)
-    single_leg = None
-    if args.single_pass_leg and not single and not args.backtrack and prec == "fp32":
-        single_leg = single_pass_run(args, wl, args.steps)
+    other_leg = None
+    if args.other_mode_leg and not args.backtrack and prec == "fp32":
+        other_leg = other_mode_run(args, wl, args.steps, single=not single)
+        if ceiling is not None and not single:
+            other_leg["frac_of_gather_ceiling"] = ceiling["relabelled_fp32_ms"] / (
+                other_leg["prepass_ms"] + other_leg["k_single_ms"])
+        elif ceiling is not None:
+            other_leg["frac_of_gather_ceiling"] = ceiling["relabelled_fp32_ms"] / other_leg["spmm_ms"]
     del wl
     torch.cuda.empty_cache()
     serving = None
@@ -1042,7 +1076,7 @@ def main() -> int:
         "cpu_baseline": cpu,
         "gather_ceiling": ceiling,
         "backtracking_run": backtracking,
-        "single_pass_run": single_leg,
+        ("two_pass_run" if single else "single_pass_run"): other_leg,
         "serving": serving,
         "mixed_time_to_target": mixed_target,
         "artificial_two_cluster": artificial,
