@@ -1833,6 +1833,130 @@ __device__ __forceinline__ double block_sum_256(double v) {
     return r;
 }
 
+// The loss terms sum_i <x_i, (S_off X)_i> of a symmetric S, for a read-out:
+// from the entries on and below the diagonal only (the one on it at half
+// weight; the sum is doubled by the controller), walked as one flat
+// sequence of nonzeros rather than row by row, so that the pass runs at the
+// memory system's rate on its gathers instead of waiting on every row's
+// chain of dependent loads.  Each team of GS lanes (16 bytes of a row each)
+// takes chunks of LOSS_CHUNK consecutive nonzeros, finds the chunk's first
+// row by binary search, and walks the rows it touches: the sum z of a row's
+// gathered terms, dotted with the row's own x_i when the walk leaves the row
+// (a row split between chunks gives each chunk its part of the dot).  The
+// next row's end and x_i are loaded ahead.  An entry is gathered in the pass
+// that loads it when its column is at most the current row (then it is
+// below the diagonal of its own row, which can only be later); the rare
+// entry whose row is reached only during the pass is gathered when it is
+// added.  Per-lane FP64 dots, summed in a fixed order into part[blockIdx];
+// a persistent grid walks the chunks.  At n = 7e7, c = 32 the pass takes
+// about 20 ms against 28 ms for the whole product with its epilogue; the
+// flat gather probe does the same gathers in 11.5 ms: the walk still waits
+// at row boundaries (eight entries per pass instead of four measured the
+// same).
+constexpr int64_t LOSS_CHUNK = 2048;
+template <typename T, int CP, int DEPTH = 4>
+__global__ __launch_bounds__(256) void k_loss_lower(const int64_t *__restrict__ row_ptr,
+                                                    const int32_t *__restrict__ col,
+                                                    const T *__restrict__ val, const T *__restrict__ X,
+                                                    int64_t n, int64_t nnz, double *__restrict__ part) {
+    using Cfg = TeamCfg<T, CP, 1>;
+    constexpr int GS = Cfg::GS, TEAMS = Cfg::TEAMS, NE = Cfg::LANE_ELEMS;
+    const int tid = threadIdx.x, team = tid / GS, sub = tid % GS;
+    const int64_t nchunks = (nnz + LOSS_CHUNK - 1) / LOSS_CHUNK;
+    const int64_t team_id = (int64_t)blockIdx.x * TEAMS + team, nteams = (int64_t)gridDim.x * TEAMS;
+    double dot = 0.0;
+    auto load_x = [&](int64_t r, T (&x)[NE]) {
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            x[q] = (T)0;
+        if (r < n)
+            GatherLoad<T, NE>::load(X + r * CP + sub * NE, x);
+    };
+    for (int64_t k = team_id; k < nchunks; k += nteams) {
+        const int64_t e0 = k * LOSS_CHUNK, e1 = e0 + LOSS_CHUNK < nnz ? e0 + LOSS_CHUNK : nnz;
+        // the last row whose range starts at or before e0
+        int64_t lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (row_ptr[mid] <= e0)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        int64_t row = lo;
+        int64_t rend = row_ptr[row + 1];
+        int64_t rend2 = row + 2 <= n ? row_ptr[row + 2] : nnz;
+        T xi[NE], xn[NE], z[NE];
+        load_x(row, xi);
+        load_x(row + 1, xn);
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            z[q] = (T)0;
+        int32_t jn[DEPTH];
+        T sn[DEPTH];
+#pragma unroll
+        for (int u = 0; u < DEPTH; ++u) {
+            const int64_t e = e0 + u;
+            jn[u] = e < e1 ? col[e] : -1;
+            sn[u] = e < e1 ? val[e] : (T)0;
+        }
+        for (int64_t eb = e0; eb < e1; eb += DEPTH) {
+            int32_t j[DEPTH];
+            T s[DEPTH], g[DEPTH][NE];
+            bool have[DEPTH];
+#pragma unroll
+            for (int u = 0; u < DEPTH; ++u) {
+                j[u] = jn[u];
+                s[u] = sn[u];
+                have[u] = j[u] >= 0 && j[u] <= row;
+#pragma unroll
+                for (int q = 0; q < NE; ++q)
+                    g[u][q] = (T)0;
+                if (have[u])
+                    GatherLoad<T, NE>::load(X + (int64_t)j[u] * CP + sub * NE, g[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < DEPTH; ++u) {
+                const int64_t e = eb + DEPTH + u;
+                jn[u] = e < e1 ? col[e] : -1;
+                sn[u] = e < e1 ? val[e] : (T)0;
+            }
+#pragma unroll
+            for (int u = 0; u < DEPTH; ++u) {
+                const int64_t e = eb + u;
+                if (e >= e1)
+                    break;
+                while (e >= rend) {   // the walk leaves the row
+#pragma unroll
+                    for (int q = 0; q < NE; ++q) {
+                        dot += (double)z[q] * (double)xi[q];
+                        z[q] = (T)0;
+                        xi[q] = xn[q];
+                    }
+                    ++row;
+                    rend = rend2;
+                    rend2 = row + 2 <= n ? row_ptr[row + 2] : nnz;
+                    load_x(row + 1, xn);
+                }
+                if (j[u] > row)
+                    continue;   // above the diagonal: its mirror entry counts it
+                const T w = j[u] == row ? (T)0.5 * s[u] : s[u];
+                if (!have[u])
+                    GatherLoad<T, NE>::load(X + (int64_t)j[u] * CP + sub * NE, g[u]);
+#pragma unroll
+                for (int q = 0; q < NE; ++q)
+                    z[q] += w * g[u][q];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NE; ++q)
+            dot += (double)z[q] * (double)xi[q];
+    }
+    const double tot = block_sum_256(dot);
+    if (tid == 0)
+        part[blockIdx.x] = tot;
+}
+
 // K such sums at once, each in exactly the order of block_sum_256 (so each
 // result has the same bits), with one pair of barriers for all of them.
 template <int K>
@@ -1938,7 +2062,17 @@ __device__ __forceinline__ void control_body(const Inst &I, int mode) {
     if (tid == 0) {
         // deferred: the products carry no terms; the fused kernel (or the
         // evaluation pass) summed them for the current iterate
-        const double tr_p = st->defer ? sc[FS_TRC] : tr_total;
+        double tr_p = st->defer ? sc[FS_TRC] : tr_total;
+        if (mode == 3) {
+            // the read-out's terms come from the entries on and below the
+            // diagonal (k_loss_lower): twice them, plus the unit diagonal's
+            // sum_i ||x_i||^2, the trace of the read-out's Gram matrix
+            double gdiag = 0.0;
+            if (I.diag_unit)
+                for (int k = 0; k < c; ++k)
+                    gdiag += Gp[k * CPM + k];
+            tr_p = 2.0 * tr_total + gdiag;
+        }
         const double f_p = st->s2 + gp_sq - 2.0 * tr_p;
         int accept = 1;
         if (mode == 0) {
