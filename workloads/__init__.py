@@ -27,7 +27,9 @@ Recipes (documented with the inputs they stand in for in the design doc):
 """
 from __future__ import annotations
 
+import json
 import math
+import os
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -335,31 +337,63 @@ def chung_lu_planted(n: int, c: int, mean_deg: float, gamma: float, wmax: float,
                          realised_max_deg=int(deg.max())))
 
 
-# The five configurations of the fuzzy-clustering workload family.
+# The five configurations of the fuzzy-clustering workload family, as stored
+# in configs.json (generator, parameters, seed and how each is run).
+CONFIGS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "configs.json")
+_DT = {"fp64": torch.float64, "fp32": torch.float32}
+
+
+def configs() -> dict:
+    """The configuration records of configs.json, by name (C1..C5)."""
+    with open(CONFIGS_PATH) as fh:
+        return {k: v for k, v in json.load(fh).items() if not k.startswith("_")}
+
+
+def from_config(name: str, seed: int | None = None, device="cpu", n: int | None = None,
+                **overrides) -> Workload:
+    """The workload of configuration `name` (C1..C4), with its stored seed
+    unless one is given; n (and any generator keyword) may be overridden to
+    build a smaller instance of the same family."""
+    rec = configs()[name]
+    p = dict(rec["params"])
+    p.update(overrides)
+    seed = rec["seed"] if seed is None else seed
+    n_stored = p.pop("n")
+    n = n_stored if n is None else n
+    vdt, udt = _DT[p.pop("values")], _DT[p.pop("iterates")]
+    if rec["generator"] == "er_planted":
+        return er_planted(n, p.pop("c"), p.pop("avg_deg"), p.pop("sigma"), seed, device=device,
+                          val_dtype=vdt, u_dtype=udt, **p)
+    if rec["generator"] == "chung_lu_planted":
+        return chung_lu_planted(n, p.pop("c"), p.pop("mean_deg"), p.pop("gamma"), p.pop("wmax"),
+                                p.pop("sigma"), seed, device=device, val_dtype=vdt, u_dtype=udt, **p)
+    raise ValueError(f"{name}: no single-instance generator ({rec['generator']})")
+
+
 def config_small_fp64(seed: int = 0, device="cpu", u0: str = "dirichlet") -> Workload:
-    """n=2,000, c=8: Dirichlet(0.3) planted rows over 8 clusters, ER pattern of
-    average degree 20 (40,000 stored nnz), sigma=0.02, FP64 values."""
-    return er_planted(2000, 8, 20.0, 0.02, seed, plant="dirichlet", alpha=0.3, u0=u0,
-                      device=device, val_dtype=torch.float64, u_dtype=torch.float64)
+    """C1: n=2,000, c=8: Dirichlet(0.3) planted rows over 8 clusters, ER pattern
+    of average degree 20 (40,000 stored nnz), sigma=0.02, FP64 values."""
+    return from_config("C1", seed, device, u0=u0)
 
 
 def config_medium(seed: int = 0, device="cpu", n: int = 1_000_000) -> Workload:
-    """n=1e6, c=32: 32 overlapping communities (1-3 per node, Dirichlet(0.2)),
-    ER pattern of average degree 30 (~3e7 stored nnz), sigma=0.05, FP32."""
-    return er_planted(n, 32, 30.0, 0.05, seed, device=device)
+    """C2: n=1e6, c=32: 32 overlapping communities (1-3 per node,
+    Dirichlet(0.2)), ER pattern of average degree 30 (~3e7 stored nnz),
+    sigma=0.05, FP32."""
+    return from_config("C2", seed, device, n)
 
 
 def config_full_power_law(seed: int = 0, device="cpu", n: int = 70_000_000) -> Workload:
-    """n=7e7, c=32: power-law degrees (gamma 2.1, mean 20, max 50,000),
+    """C3: n=7e7, c=32: power-law degrees (gamma 2.1, mean 20, max 50,000),
     ~1.4e9 stored nnz, planted values as in the medium config, FP32."""
-    return chung_lu_planted(n, 32, 20.0, 2.1, 50_000.0, 0.05, seed, device=device)
+    return from_config("C3", seed, device, n)
 
 
 def config_mixed_full(seed: int = 0, device="cpu", n: int = 70_000_000) -> Workload:
-    """The medium generator at n=7e7: ER pattern of average degree 30
+    """C4: the medium generator at n=7e7: ER pattern of average degree 30
     (~2.1e9 stored nnz), 32 overlapping communities, sigma=0.05, FP32 values
     (the mixed-precision solver keeps its own FP16 copy)."""
-    return er_planted(n, 32, 30.0, 0.05, seed, device=device)
+    return from_config("C4", seed, device, n)
 
 
 def two_cluster_er(seed: int = 0, device="cpu", n1: int = 500_000, n2: int = 250_000,
@@ -404,11 +438,17 @@ def two_cluster_er(seed: int = 0, device="cpu", n1: int = 500_000, n2: int = 250
 
 
 def serving_request(req_id: int, device="cpu", base_seed: int = 0) -> Workload:
-    """One serving request: n log-uniform in [500, 2e5], c in {4,8,16,32,64},
-    average degree U(10, 40), planted communities, ER pattern."""
+    """One request of C5: n log-uniform in [500, 2e5], c in {4,8,16,32,64},
+    average degree U(10, 40), planted communities, ER pattern (the ranges as
+    stored in configs.json)."""
+    p = configs()["C5"]["params"]
     g = _gen(base_seed + req_id, 6, "cpu")
     u = torch.rand(3, generator=g, dtype=torch.float64)
-    n = int(round(math.exp(math.log(500) + float(u[0]) * (math.log(200_000) - math.log(500)))))
-    c = [4, 8, 16, 32, 64][min(4, int(float(u[1]) * 5))]
-    d = 10.0 + 30.0 * float(u[2])
-    return er_planted(n, c, d, 0.05, base_seed + req_id, device=device)
+    lo, hi = (math.log(x) for x in p["n_loguniform"])
+    n = int(round(math.exp(lo + float(u[0]) * (hi - lo))))
+    choices = p["c_choices"]
+    c = choices[min(len(choices) - 1, int(float(u[1]) * len(choices)))]
+    d0, d1 = p["avg_deg_uniform"]
+    d = d0 + (d1 - d0) * float(u[2])
+    return er_planted(n, c, d, p["sigma"], base_seed + req_id, alpha=p["alpha"], kmax=p["kmax"],
+                      device=device)
