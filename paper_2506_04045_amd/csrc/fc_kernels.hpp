@@ -1836,9 +1836,9 @@ __device__ __forceinline__ double block_sum_256(double v) {
 // The loss terms sum_i <x_i, (S_off X)_i> of a symmetric S, for a read-out:
 // from the entries on and below the diagonal only (the one on it at half
 // weight; the sum is doubled by the controller), walked as one flat
-// sequence of nonzeros rather than row by row, so that the pass runs at the
-// memory system's rate on its gathers instead of waiting on every row's
-// chain of dependent loads.  Each team of GS lanes (16 bytes of a row each)
+// sequence of nonzeros rather than row by row (a row-by-row pass over half
+// the entries measured nearly as slow as the whole product: its teams wait
+// on every row's chain of dependent loads).  Each team of GS lanes (16 bytes of a row each)
 // takes chunks of LOSS_CHUNK consecutive nonzeros, finds the chunk's first
 // row by binary search, and walks the rows it touches: the sum z of a row's
 // gathered terms, dotted with the row's own x_i when the walk leaves the row
