@@ -1838,9 +1838,10 @@ __device__ __forceinline__ double block_sum_256(double v) {
 // weight; the sum is doubled by the controller), walked as one flat
 // sequence of nonzeros rather than row by row (a row-by-row pass over half
 // the entries measured nearly as slow as the whole product: its teams wait
-// on every row's chain of dependent loads).  Each team of GS lanes (16 bytes of a row each)
-// takes chunks of LOSS_CHUNK consecutive nonzeros, finds the chunk's first
-// row by binary search, and walks the rows it touches: the sum z of a row's
+// on every row's chain of dependent loads).  Each team of GS lanes (16
+// bytes of a row each) takes chunks of LOSS_CHUNK consecutive nonzeros,
+// finds the chunk's first row by binary search, and walks the rows it
+// touches: the sum z of a row's
 // gathered terms, dotted with the row's own x_i when the walk leaves the row
 // (a row split between chunks gives each chunk its part of the dot).  The
 // next row's end and x_i are loaded ahead.  An entry is gathered in the pass
