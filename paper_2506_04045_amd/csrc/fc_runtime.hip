@@ -574,8 +574,9 @@ fc_status launch_single_eval_t(fc_solver *h) {
     constexpr int CPM = CP < 16 ? 16 : CP;
     hipStream_t s = h->stream;
     const int ld = CPM * CPM;
-    hipLaunchKernelGGL((k_gram<T, CP>), dim3(h->g_gram), dim3(256), 0, s, (const T *)h->X[0], h->n,
-                       h->d_part_gram, (int64_t)ld);
+    const T *Xbar = (const T *)h->X[h->h.role[ROLE_C]];   // the iterate being read out
+    hipLaunchKernelGGL((k_gram<T, CP>), dim3(h->g_gram), dim3(256), 0, s, Xbar, h->n, h->d_part_gram,
+                       (int64_t)ld);
     launch_reduce(h->d_part_gram, (int64_t)h->g_gram * 4, ld, ld, h->d_red_mats, s);
     // only the loss terms of the read-out iterate are needed: a symmetric S
     // gives them from its entries on and below the diagonal, in one flat pass
@@ -587,7 +588,7 @@ fc_status launch_single_eval_t(fc_solver *h) {
     int64_t g_loss = std::min<int64_t>((int64_t)device_cus() * 16, cdiv(chunks, 256 / TeamCfg<T, CP, 1>::GS));
     g_loss = std::max<int64_t>(1, std::min<int64_t>(g_loss, (int64_t)I.g_spmm + I.g_comb));   // partial slots held
     hipLaunchKernelGGL((k_loss_lower<T, CP>), dim3((unsigned)g_loss), dim3(256), 0, s, I.row_ptr, I.col,
-                       (const T *)I.val, (const T *)h->X[h->h.role[ROLE_C]], I.n, h->nnz, I.part_spmm);
+                       (const T *)I.val, Xbar, I.n, h->nnz, I.part_spmm);
     I.g_spmm = (int32_t)g_loss;
     I.g_comb = 0;
     hipLaunchKernelGGL((k_control_1<T, CPM>), dim3(1), dim3(256), 0, s, I, 3);
