@@ -112,3 +112,14 @@ def test_community_order_groups_by_dominant_planted_community(graph):
     deg = np.diff(graph.row_ptr.numpy())
     key = list(zip(dom[perm], -deg[perm]))
     assert key == sorted(key)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """--gpus above 1 exits with a message before anything touches a GPU."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120, cwd=root)
+    assert out.returncode == 2 and "one GPU" in out.stderr
