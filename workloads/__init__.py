@@ -9,7 +9,7 @@ Every draw comes from a ``torch.Generator`` seeded from (seed, stream), so a
 workload is a pure function of its parameters and the device it is drawn on
 (CPU and GPU generators produce different streams; tests draw on the CPU).
 
-Recipes (documented with the inputs they stand in for in the design doc):
+Recipes (the five benchmark configurations built from them are in configs.json):
 
 * ``er_planted``   -- Erdos-Renyi pattern with m distinct unordered pairs
   (i != j) drawn uniformly; values s_ij = clip(u*_i . u*_j + N(0, sigma^2), 0, 1),
