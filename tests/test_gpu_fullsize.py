@@ -99,10 +99,17 @@ def test_power_law_full_size_fp32(fc):
     with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, wl.c, wl.U0, accelerate=True, step=0.0,
                    reorder="degree", single_pass=True) as s:
         info_c = s.step(12)
-        du = float((s.get_u() - Ua).abs().max())
+        Uc = s.get_u()
+        du = float((Uc - Ua).abs().max())
+    # its read-out loss (the lower-triangle pass over the relabelled matrix)
+    # against the stateless objective of the same iterate (the whole product,
+    # on the caller's numbering)
+    f_obj = fc.objective(wl.row_ptr, wl.col_idx, wl.val, Uc)
     print(f"full-size 12 iterations, single pass vs deferred mode: max|dU| {du:.2e}, "
-          f"f {info_c.f:.9e} vs {info_a.f:.9e}")
+          f"f {info_c.f:.9e} vs {info_a.f:.9e}; read-out vs objective {info_c.f - f_obj:.3e}")
     assert du <= 1e-6 and abs(info_c.f - info_a.f) <= 1e-6 * abs(info_a.f)
+    assert abs(info_c.f - f_obj) <= 1e-9 * abs(f_obj)
+    del Uc
     del Ua, wl
     torch.cuda.empty_cache()
 
