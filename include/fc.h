@@ -167,7 +167,9 @@ typedef enum { FC_REORDER_NONE = 0, FC_REORDER_DEGREE = 1 } fc_reorder;
  * (the default mode stores S Xbar and re-forms Y from two iterates).  The
  * structured loss of Alg. 3 needs S Xbar_n, which this mode never forms
  * inside the iteration: it is evaluated once at the end of every fc_step /
- * fc_solve call (one extra sparse product), so info.f is the loss of the
+ * fc_solve call, by one pass over the stored entries on and below the
+ * diagonal (the cross term sum_i <xbar_i, (S Xbar)_i> is twice that half's
+ * sum, diagonal once, which holds because S = S^T), so info.f is the loss of the
  * returned iterate and info.f_prev that of the previous read-out, and the
  * history holds losses only at read-outs (NaN elsewhere).  The gradient-
  * mapping stop is available, the loss stop is not (FC_ERR_UNSUPPORTED).
