@@ -100,6 +100,15 @@ def copy_bandwidth(mib: int = 4096) -> float:
     return gbs
 
 
+def solver_order(args, power_law: bool = True):
+    """The `reorder` argument of a solver: the library's own orders by name;
+    a Cuthill-McKee or community order as the array built for the power-law
+    workload (other workloads take degree order then)."""
+    if args.reorder in ("none", "degree"):
+        return args.reorder
+    return args.given_order if power_law else "degree"
+
+
 def other_mode_run(args, wl, steps: int, single: bool) -> dict:
     """The iteration in the mode the headline does not use, on the same
     instance and timed the same way (one fc_step call of `steps` iterations
@@ -110,7 +119,7 @@ def other_mode_run(args, wl, steps: int, single: bool) -> dict:
     import paper_2506_04045_amd as fc
     t0 = time.perf_counter()
     s = fc.Solver(wl.row_ptr, wl.col_idx, wl.val, args.c, wl.U0, precision="fp32", accelerate=True,
-                  step=0.0, reorder=args.reorder, single_pass=single, defer_loss=not single)
+                  step=0.0, reorder=solver_order(args), single_pass=single, defer_loss=not single)
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     s.step(args.warmup)
@@ -168,7 +177,7 @@ def backtracking_run(args, wl) -> dict:
     import paper_2506_04045_amd as fc
     t0 = time.perf_counter()
     s = fc.Solver(wl.row_ptr, wl.col_idx, wl.val, args.c, wl.U0, precision=args.precision,
-                  accelerate=True, step=0.0, backtrack=True, reorder=args.reorder)
+                  accelerate=True, step=0.0, backtrack=True, reorder=solver_order(args))
     torch.cuda.synchronize()
     setup = time.perf_counter() - t0
     w = s.step(2)
@@ -683,7 +692,7 @@ def mixed_target_bench(args) -> dict:
     def fp32_run():
         # tau = 1/L_thm with ||S||_F for ||S||_2, as the paper's experiments do
         with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 32, wl.U0, precision="fp32", step=0.0,
-                       norm_estimate="frobenius", reorder=args.reorder,
+                       norm_estimate="frobenius", reorder=solver_order(args, power_law=False),
                        defer_loss=bool(args.defer_loss)) as s:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -699,7 +708,7 @@ def mixed_target_bench(args) -> dict:
     def mixed_run(tau, target):
         elapsed, it, f_mixed = 0.0, 0, math.inf
         with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 32, wl.U0, precision="mixed", step=tau,
-                       reorder=args.reorder, defer_loss=bool(args.defer_loss)) as s:
+                       reorder=solver_order(args, power_law=False), defer_loss=bool(args.defer_loss)) as s:
             chunk = max(1, K - 5)
             while it < 2 * K:
                 torch.cuda.synchronize()
@@ -734,7 +743,7 @@ def mixed_target_bench(args) -> dict:
     return {
         "workload": (f"ER average degree 30, n={args.n:,}, c=32, planted communities sigma 0.05, "
                      f"unit diagonal, FISTA tau=1/L_thm with ||S||_F, articles relabelled: "
-                     f"{args.reorder}"),
+                     f"{solver_order(args, False)}"),
         "target": "f <= f_FP32(K) + 1e-6 (f(U0) - f_FP32(K)), objective on the FP32 values",
         "K": K, "fp32": {"iters": K, "seconds": t_fp32, "iters_per_s": K / t_fp32, "f": f_k_check,
                          "seconds_each_run": t_fp32s},
@@ -795,10 +804,10 @@ def artificial_bench(args) -> dict:
     labels = wl.meta["labels"].numpy()
     out = {"workload": (f"two-cluster ER (500,000 + 250,000 nodes, expected degrees 1,200 / "
                         f"1,600, 200 bridges), {wl.nnz:,} stored nnz, C=2, S=A+I, tau=5e-7, "
-                        f"start: every node in cluster 2, articles relabelled: {args.reorder}")}
+                        f"start: every node in cluster 2, articles relabelled: {solver_order(args, False)}")}
     for name, acc in (("gpa", False), ("fista", True)):
         with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 2, wl.U0, accelerate=acc, step=5e-7,
-                       reorder=args.reorder, defer_loss=bool(args.defer_loss)) as s:
+                       reorder=solver_order(args, power_law=False), defer_loss=bool(args.defer_loss)) as s:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             info = s.step(10)
@@ -824,8 +833,10 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=70_000_000)
     ap.add_argument("--c", type=int, default=32)
     ap.add_argument("--precision", choices=["fp32", "mixed"], default="fp32")
-    ap.add_argument("--reorder", choices=["none", "degree"], default="degree",
-                    help="internal renumbering of the articles (set up in fc_create, untimed)")
+    ap.add_argument("--reorder", choices=["none", "degree", "cm", "community"], default="degree",
+                    help="internal renumbering of the articles (set up in fc_create, untimed); "
+                         "cm and community are built here and handed to the library as a given "
+                         "order for the power-law legs (the other workloads then use degree)")
     ap.add_argument("--backtrack", action="store_true",
                     help="Beck-Teboulle backtracking (L0 = L_thm/100) instead of the constant step")
     ap.add_argument("--defer-loss", type=int, default=1,
@@ -926,6 +937,18 @@ def main() -> int:
     log(f"generated nnz={wl.nnz:,} (mean degree {wl.meta['realised_mean_deg']:.2f}, max "
         f"{wl.meta['realised_max_deg']:,}) in {time.perf_counter() - t0:.1f} s")
 
+    if args.reorder in ("cm", "community"):
+        t0 = time.perf_counter()
+        if args.reorder == "cm":
+            perm, reached = cuthill_mckee_order(wl.row_ptr, wl.col_idx)
+            log(f"Cuthill-McKee order: {reached:,} rows reached")
+        else:
+            perm = community_order(wl, args.seed, args.c)
+        args.given_order = perm.to(torch.int32).cpu().numpy()
+        del perm
+        torch.cuda.empty_cache()
+        log(f"{args.reorder} order built in {time.perf_counter() - t0:.1f} s")
+
     prec = args.precision
     t0 = time.perf_counter()
     single = bool(args.single_pass) and not args.backtrack and prec == "fp32"
@@ -935,8 +958,8 @@ def main() -> int:
     n_long, nnz_long = int(long_rows.sum()), int(deg[long_rows].sum())
     del deg, long_rows
     solver = fc.Solver(wl.row_ptr, wl.col_idx, wl.val, args.c, wl.U0, precision=prec,
-                       accelerate=True, step=0.0, backtrack=args.backtrack, reorder=args.reorder,
-                       defer_loss=defer, single_pass=single)
+                       accelerate=True, step=0.0, backtrack=args.backtrack,
+                       reorder=solver_order(args), defer_loss=defer, single_pass=single)
     torch.cuda.synchronize()
     log(f"solver created in {time.perf_counter() - t0:.1f} s")
 

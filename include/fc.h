@@ -121,10 +121,13 @@ typedef struct {
     const double *step_schedule; /* host: tau_n for n = 1..step_schedule_len, copied at
                                     fc_create; used by FC_STEP_FIXED when non-NULL */
     int32_t step_schedule_len;
-    int32_t reorder;           /* fc_reorder: FC_REORDER_NONE (default) or
-                                  FC_REORDER_DEGREE, see below */
+    int32_t reorder;           /* fc_reorder: FC_REORDER_NONE (default),
+                                  FC_REORDER_DEGREE or FC_REORDER_GIVEN, see below */
     int32_t defer_loss;        /* 1: deferred loss evaluation, see below (default 0) */
     int32_t single_pass;       /* 1: single-pass iteration, see below (default 0) */
+    const int32_t *perm;       /* host, n entries, FC_REORDER_GIVEN only: internal row
+                                  i is the caller's row perm[i]; read during
+                                  fc_create only (default NULL) */
 } fc_options;
 
 /* Internal numbering of the articles.  FC_REORDER_DEGREE renumbers them by
@@ -137,9 +140,18 @@ typedef struct {
  * the cross-article reductions (share, the loss terms) changes, so results
  * agree with FC_REORDER_NONE to rounding.  On power-law graphs it places the
  * rows that most nonzeros gather next to each other, which raises cache reuse
- * in the sparse product.  Checkpoints record the choice: fc_set_state
- * rejects a state taken with the other numbering. */
-typedef enum { FC_REORDER_NONE = 0, FC_REORDER_DEGREE = 1 } fc_reorder;
+ * in the sparse product.  FC_REORDER_GIVEN takes the caller's order instead
+ * (options.perm, a host array), for orders built outside the library, such as
+ * a breadth-first (Cuthill-McKee) or community order.  fc_create checks on the
+ * host that perm holds every row of 0..n-1 exactly once, before any device
+ * work reads it, and fails with FC_ERR_INVALID_ARG otherwise.  It then keeps
+ * the same permuted copy of S as for FC_REORDER_DEGREE, with the same results
+ * up to rounding.  Given the descending-degree order itself, results equal
+ * FC_REORDER_DEGREE bit for bit.  Relabelling needs n < 2^31.  Checkpoints
+ * record the mode, and for FC_REORDER_GIVEN a 64-bit fingerprint (FNV-1a) of
+ * perm.  fc_set_state rejects a state taken under another numbering.  The
+ * serving engine does not accept FC_REORDER_GIVEN (FC_ERR_UNSUPPORTED). */
+typedef enum { FC_REORDER_NONE = 0, FC_REORDER_DEGREE = 1, FC_REORDER_GIVEN = 2 } fc_reorder;
 
 /* Deferred loss evaluation (defer_loss = 1, constant or scheduled steps only:
  * backtracking needs each trial's loss at once and rejects it).  The

@@ -91,8 +91,8 @@ def _options(c: int, precision: str = "fp32", diag: str = "unit", accelerate: bo
              step: float = 0.0, backtrack: bool = False, L0: float = 0.0, eta: float = 2.0,
              max_iter: int = 100, check_every: int = 16, tol_loss: float = math.nan,
              tol_pgrad: float = 0.0, validate: bool = False,
-             norm_estimate: str = "power", reorder: str = "none",
-             defer_loss: bool = False, single_pass: bool = False) -> N.Options:
+             norm_estimate: str = "power", reorder="none",
+             defer_loss: bool = False, single_pass: bool = False, n=None) -> N.Options:
     opt = N.default_options()
     opt.c = int(c)
     opt.precision = _PREC[precision]
@@ -108,7 +108,19 @@ def _options(c: int, precision: str = "fp32", diag: str = "unit", accelerate: bo
     opt.tol_pgrad = float(tol_pgrad)
     opt.validate = int(bool(validate))
     opt.norm_estimate = {"power": 0, "frobenius": 1}[norm_estimate]
-    opt.reorder = {"none": 0, "degree": 1}[reorder]
+    if isinstance(reorder, str):
+        opt.reorder = {"none": 0, "degree": 1}[reorder]
+    else:   # a given order: internal row i is the caller's row reorder[i]
+        src = reorder.cpu().numpy() if torch.is_tensor(reorder) else reorder
+        wide = np.asarray(src, dtype=np.int64)
+        if wide.ndim != 1 or (n is not None and wide.shape[0] != n):
+            raise ValueError(f"a given order holds the {n} row indices, one each")
+        if wide.size and (wide.min() < 0 or wide.max() > np.iinfo(np.int32).max):
+            raise ValueError("a given order holds row indices 0..n-1")
+        perm = np.ascontiguousarray(wide, dtype=np.int32)
+        opt.reorder = N.FC_REORDER_GIVEN
+        opt.perm = perm.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        opt._perm_keep = perm   # alive while the options are
     opt.defer_loss = int(bool(defer_loss))
     opt.single_pass = int(bool(single_pass))
     return opt
@@ -155,7 +167,7 @@ class Solver:
                  backtrack: bool = False, L0: float = 0.0, eta: float = 2.0,
                  max_iter: int = 100, check_every: int = 16, tol_loss: float = math.nan,
                  tol_pgrad: float = 0.0, validate: bool = False, step_schedule=None,
-                 norm_estimate: str = "power", reorder: str = "none", defer_loss: bool = False,
+                 norm_estimate: str = "power", reorder="none", defer_loss: bool = False,
                  single_pass: bool = False, stream=None):
         lib = N.load()
         self._csr = _CsrView(row_ptr, col_idx, val)
@@ -164,7 +176,7 @@ class Solver:
         self.accelerate = bool(accelerate)
         opt = _options(c, precision, diag, accelerate, step, backtrack, L0, eta, max_iter,
                        check_every, tol_loss, tol_pgrad, validate, norm_estimate, reorder,
-                       defer_loss, single_pass)
+                       defer_loss, single_pass, n=self.n)
         self._sched = None
         if step_schedule is not None:
             self._sched = np.ascontiguousarray(step_schedule, dtype=np.float64)

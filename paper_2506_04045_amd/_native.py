@@ -19,6 +19,7 @@ FC_F64, FC_F32, FC_F16, FC_BF16 = 0, 1, 2, 3
 FC_PREC_FP64, FC_PREC_FP32, FC_PREC_MIXED = 0, 1, 2
 FC_DIAG_STORED, FC_DIAG_UNIT = 0, 1
 FC_STEP_FIXED, FC_STEP_BACKTRACK = 0, 1
+FC_REORDER_NONE, FC_REORDER_DEGREE, FC_REORDER_GIVEN = 0, 1, 2
 FC_STOP_NONE, FC_STOP_MAXITER, FC_STOP_LOSS, FC_STOP_PGRAD, FC_STOP_ERROR = 0, 1, 2, 3, 4
 
 STATUS_NAMES = {0: "FC_OK", 1: "FC_ERR_INVALID_ARG", 2: "FC_ERR_UNSUPPORTED",
@@ -53,7 +54,8 @@ class Options(ctypes.Structure):
                 ("validate", ctypes.c_int32), ("norm_estimate", ctypes.c_int32),
                 ("step_schedule", ctypes.POINTER(ctypes.c_double)),
                 ("step_schedule_len", ctypes.c_int32), ("reorder", ctypes.c_int32),
-                ("defer_loss", ctypes.c_int32), ("single_pass", ctypes.c_int32)]
+                ("defer_loss", ctypes.c_int32), ("single_pass", ctypes.c_int32),
+                ("perm", ctypes.POINTER(ctypes.c_int32))]
 
 
 class Info(ctypes.Structure):

@@ -1,7 +1,8 @@
 // fc_host.hpp -- host-side planning of the fuzzy-clustering solver, in plain
 // C++17 with no HIP dependency: the structural check of a CSR row-pointer
-// array, the plan of the sparse product's long rows, and the launch-grid rule
-// of the fused kernel that single solves and served instances share.  The
+// array, the check and fingerprint of a caller-given article order, the plan
+// of the sparse product's long rows, and the launch-grid rule of the fused
+// kernel that single solves and served instances share.  The
 // library includes it; the CPU tests compile it alone, under the address and
 // undefined-behaviour sanitizers.
 #pragma once
@@ -42,6 +43,43 @@ inline int check_row_ptr(const int64_t *rp, int64_t n, int64_t nnz, int64_t *bad
         return RP_LAST;
     }
     return RP_OK;
+}
+
+// Check of a caller-given article order: perm[i] is the caller's row placed
+// at internal row i, so perm must hold every row of 0..n-1 exactly once.
+// Returns PERM_OK, or the first violation in index order: PERM_RANGE (an entry
+// outside 0..n-1) or PERM_REPEAT (an entry seen before), with its index i in
+// *bad_index when given.
+enum { PERM_OK = 0, PERM_RANGE = 1, PERM_REPEAT = 2 };
+inline int check_permutation(const int32_t *perm, int64_t n, int64_t *bad_index) {
+    if (bad_index)
+        *bad_index = 0;
+    std::vector<uint8_t> seen((size_t)std::max<int64_t>(n, 0), 0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t p = perm[i];
+        if (p < 0 || p >= n || seen[(size_t)p]) {
+            if (bad_index)
+                *bad_index = i;
+            return p < 0 || p >= n ? PERM_RANGE : PERM_REPEAT;
+        }
+        seen[(size_t)p] = 1;
+    }
+    return PERM_OK;
+}
+
+// 64-bit FNV-1a hash of an order's bytes (entries little-endian, in index
+// order): a checkpoint records it, so a state is resumed only under the order
+// it was taken with.
+inline uint64_t order_fingerprint(const int32_t *perm, int64_t n) {
+    uint64_t h = 0xcbf29ce484222325ull;   // FNV offset basis
+    for (int64_t i = 0; i < n; ++i) {
+        const uint32_t v = (uint32_t)perm[i];
+        for (int b = 0; b < 4; ++b) {
+            h ^= (v >> (8 * b)) & 0xffu;
+            h *= 0x100000001b3ull;            // FNV prime
+        }
+    }
+    return h;
 }
 
 // The plan of the rows longer than SPMM_LIGHT_MAX, in row order: medium rows

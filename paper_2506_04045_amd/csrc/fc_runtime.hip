@@ -412,6 +412,7 @@ struct fc_solver {
     int defer = 0;              // deferred loss evaluation (fixed steps)
     int single = 0;             // single-pass iteration (fixed steps)
     Inst inst_long = {};        // its sparse-product pre-pass (rows longer than light_max)
+    uint64_t perm_hash = 0;     // FNV-1a of a given order (FC_REORDER_GIVEN), else 0
     int32_t *d_perm = nullptr;  // internal row i is user row d_perm[i]
     int32_t *d_inv = nullptr;   // user row j is internal row d_inv[j]
     std::vector<void *> allocs;
@@ -796,10 +797,13 @@ namespace {
 
 // Set-up shared by fc_create and the serving engine: `hist_cap` iterations
 // of history, allocations from the stream-ordered pool when `pooled`.
-// Renumber the articles by descending degree (FC_REORDER_DEGREE): a stable
-// radix sort of the complemented row lengths gives perm, then the permuted
-// CSR is written into library-owned arrays with values of type vdt_out.
-fc_status build_degree_order(fc_solver *h, const fc_csr *S, fc_dtype vdt_out, hipStream_t s) {
+// Renumber the articles: by descending degree (FC_REORDER_DEGREE), where a
+// stable radix sort of the complemented row lengths gives perm, or in the
+// caller's order `given` (FC_REORDER_GIVEN, a host array already checked to be
+// a permutation); then the permuted CSR is written into library-owned arrays
+// with values of type vdt_out.
+fc_status build_order(fc_solver *h, const fc_csr *S, fc_dtype vdt_out, const int32_t *given,
+                      hipStream_t s) {
     const int64_t n = S->n, nnz = S->nnz;
     if (n > (int64_t)INT32_MAX)
         return fail(FC_ERR_UNSUPPORTED, "relabelling needs n < 2^31");
@@ -814,25 +818,33 @@ fc_status build_degree_order(fc_solver *h, const fc_csr *S, fc_dtype vdt_out, hi
         h->alloc(&val_new, vbytes * nnz) != hipSuccess)
         return fail(FC_ERR_OUT_OF_MEMORY, "relabelled copy of S");
     DevBuf keys, keys_out, ids, len, tmp;
-    if (dev_alloc(keys, sizeof(uint32_t) * n, s) != hipSuccess ||
-        dev_alloc(keys_out, sizeof(uint32_t) * n, s) != hipSuccess ||
-        dev_alloc(ids, sizeof(int32_t) * n, s) != hipSuccess ||
-        dev_alloc(len, sizeof(int64_t) * n, s) != hipSuccess)
+    if (dev_alloc(len, sizeof(int64_t) * n, s) != hipSuccess)
         return fail(FC_ERR_OUT_OF_MEMORY, "relabelling scratch");
     const int g = grid_1d(n, 256, 16384);
-    hipLaunchKernelGGL(k_degree_keys, dim3(g), dim3(256), 0, s, S->row_ptr, n, (uint32_t *)keys.p,
-                       (int32_t *)ids.p);
     size_t sort_bytes = 0, scan_bytes = 0;
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t *)keys.p,
-                                              (uint32_t *)keys_out.p, (const int32_t *)ids.p,
-                                              h->d_perm, (int)n, 0, 32, s));
+    if (!given) {
+        if (dev_alloc(keys, sizeof(uint32_t) * n, s) != hipSuccess ||
+            dev_alloc(keys_out, sizeof(uint32_t) * n, s) != hipSuccess ||
+            dev_alloc(ids, sizeof(int32_t) * n, s) != hipSuccess)
+            return fail(FC_ERR_OUT_OF_MEMORY, "relabelling scratch");
+        hipLaunchKernelGGL(k_degree_keys, dim3(g), dim3(256), 0, s, S->row_ptr, n, (uint32_t *)keys.p,
+                           (int32_t *)ids.p);
+        HIPCHK(hipcub::DeviceRadixSort::SortPairs(nullptr, sort_bytes, (const uint32_t *)keys.p,
+                                                  (uint32_t *)keys_out.p, (const int32_t *)ids.p,
+                                                  h->d_perm, (int)n, 0, 32, s));
+    }
     HIPCHK(hipcub::DeviceScan::InclusiveSum(nullptr, scan_bytes, (const int64_t *)len.p, rp_new + 1,
                                             (int)n, s));
     if (dev_alloc(tmp, std::max(sort_bytes, scan_bytes), s) != hipSuccess)
         return fail(FC_ERR_OUT_OF_MEMORY, "relabelling scratch");
-    HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp.p, sort_bytes, (const uint32_t *)keys.p,
-                                              (uint32_t *)keys_out.p, (const int32_t *)ids.p,
-                                              h->d_perm, (int)n, 0, 32, s));
+    if (given) {   // the caller's array is read before fc_create goes on
+        HIPCHK(hipMemcpyAsync(h->d_perm, given, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } else {
+        HIPCHK(hipcub::DeviceRadixSort::SortPairs(tmp.p, sort_bytes, (const uint32_t *)keys.p,
+                                                  (uint32_t *)keys_out.p, (const int32_t *)ids.p,
+                                                  h->d_perm, (int)n, 0, 32, s));
+    }
     hipLaunchKernelGGL(k_perm_lengths, dim3(g), dim3(256), 0, s, S->row_ptr, h->d_perm, n, h->d_inv,
                        (int64_t *)len.p);
     HIPCHK(hipMemsetAsync(rp_new, 0, sizeof(int64_t), s));
@@ -861,7 +873,7 @@ fc_status build_degree_order(fc_solver *h, const fc_csr *S, fc_dtype vdt_out, hi
     h->col = col_new;
     h->val = val_new;
     h->vdt = vdt_out;
-    h->reorder = FC_REORDER_DEGREE;
+    h->reorder = given ? FC_REORDER_GIVEN : FC_REORDER_DEGREE;
     return FC_OK;
 }
 
@@ -892,8 +904,23 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
         return fail(FC_ERR_INVALID_ARG, "step_schedule_len must be >= 1");
     if (opt->norm_estimate != 0 && opt->norm_estimate != 1)
         return fail(FC_ERR_INVALID_ARG, "norm_estimate must be 0 or 1");
-    if (opt->reorder != FC_REORDER_NONE && opt->reorder != FC_REORDER_DEGREE)
+    if (opt->reorder != FC_REORDER_NONE && opt->reorder != FC_REORDER_DEGREE &&
+        opt->reorder != FC_REORDER_GIVEN)
         return fail(FC_ERR_INVALID_ARG, "unknown reorder mode");
+    uint64_t perm_hash = 0;
+    if (opt->reorder == FC_REORDER_GIVEN) {   // checked before any device work reads it
+        if (!opt->perm)
+            return fail(FC_ERR_INVALID_ARG, "FC_REORDER_GIVEN needs options.perm");
+        if (S->n > (int64_t)INT32_MAX)
+            return fail(FC_ERR_UNSUPPORTED, "relabelling needs n < 2^31");
+        int64_t bad = 0;
+        const int pc = check_permutation(opt->perm, S->n, &bad);
+        if (pc != PERM_OK)
+            return fail(FC_ERR_INVALID_ARG,
+                        "perm is not a permutation of the rows: entry " + std::to_string(bad) +
+                            (pc == PERM_RANGE ? " is outside 0..n-1" : " repeats an earlier entry"));
+        perm_hash = order_fingerprint(opt->perm, S->n);
+    }
     if (opt->defer_loss != 0 && opt->defer_loss != 1)
         return fail(FC_ERR_INVALID_ARG, "defer_loss must be 0 or 1");
     if (opt->defer_loss && opt->step_rule != FC_STEP_FIXED)
@@ -1019,11 +1046,12 @@ fc_status create_impl(const fc_csr *S, const fc_options *opt, const void *U0, fc
             (h->shadow[k] && hipMemsetAsync(h->shadow[k], 0, (size_t)h->n * h->cp * 2, s) != hipSuccess))
             return cleanup(fail(FC_ERR_DEVICE, "clearing the iterate buffers"));
     }
-    if (opt->reorder == FC_REORDER_DEGREE) {
+    if (opt->reorder == FC_REORDER_DEGREE || opt->reorder == FC_REORDER_GIVEN) {
         const fc_dtype vout = h->prec == FC_PREC_MIXED ? FC_F16 : S->values_dtype;
-        st = build_degree_order(h, S, vout, s);
+        st = build_order(h, S, vout, opt->reorder == FC_REORDER_GIVEN ? opt->perm : nullptr, s);
         if (st != FC_OK)
             return cleanup(st);
+        h->perm_hash = perm_hash;
     } else if (h->prec == FC_PREC_MIXED && S->values_dtype == FC_F32) {
         if (h->alloc(&h->val_owned, (size_t)S->nnz * 2) != hipSuccess)
             return cleanup(fail(FC_ERR_OUT_OF_MEMORY, "half copy of S"));
@@ -1376,6 +1404,7 @@ struct CkptHeader {
     int32_t c, cp, prec, accelerate, backtrack, diag;
     int32_t hist_len, reorder;
     int32_t defer, reserved;   // reserved: the single-pass flag
+    uint64_t perm_hash;        // fingerprint of a given order (FC_REORDER_GIVEN), else 0
     DevState st;
 };
 constexpr uint64_t CKPT_MAGIC = 0x3130545043434646ull;  // "FFCCPT01"
@@ -1408,7 +1437,7 @@ fc_status fc_get_state(const fc_solver *h, void *buf, size_t *bytes) {
     hipStream_t s = h->stream;
     CkptHeader hd = {};
     hd.magic = CKPT_MAGIC;
-    hd.version = 2;
+    hd.version = 3;
     hd.header_bytes = sizeof(CkptHeader);
     hd.n = h->n;
     hd.c = h->c;
@@ -1420,6 +1449,7 @@ fc_status fc_get_state(const fc_solver *h, void *buf, size_t *bytes) {
     hd.reorder = h->reorder;
     hd.defer = h->defer;
     hd.reserved = h->single;
+    hd.perm_hash = h->perm_hash;
     hd.hist_len = hist_len;
     hd.st = h->h;
     char *p = (char *)buf;
@@ -1455,12 +1485,14 @@ fc_status fc_set_state(fc_solver *h, const void *buf, size_t bytes) {
         return fail(FC_ERR_INVALID_ARG, "checkpoint buffer too small");
     CkptHeader hd;
     std::memcpy(&hd, buf, sizeof(hd));
-    if (hd.magic != CKPT_MAGIC || hd.version != 2 || hd.header_bytes != sizeof(CkptHeader))
+    if (hd.magic != CKPT_MAGIC || hd.version != 3 || hd.header_bytes != sizeof(CkptHeader))
         return fail(FC_ERR_INVALID_ARG, "not a checkpoint of this library version");
     if (hd.n != h->n || hd.c != h->c || hd.cp != h->cp || hd.prec != (int32_t)h->prec ||
         hd.accelerate != h->accelerate || hd.backtrack != h->backtrack || hd.diag != (int32_t)h->diag ||
         hd.reorder != h->reorder || hd.defer != h->defer || hd.reserved != h->single)
         return fail(FC_ERR_INVALID_ARG, "checkpoint was taken from a solver with other n, c or options");
+    if (hd.perm_hash != h->perm_hash)
+        return fail(FC_ERR_INVALID_ARG, "checkpoint was taken under another given article order");
     if (hd.hist_len < 1 || hd.hist_len > h->hist_cap || bytes < ckpt_bytes(h, hd.hist_len))
         return fail(FC_ERR_INVALID_ARG, "checkpoint buffer truncated");
     hipStream_t s = h->stream;

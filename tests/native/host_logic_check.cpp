@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stdio.h>
 
+#include <algorithm>
 #include <random>
 #include <vector>
 
@@ -98,6 +99,46 @@ static void check_fused_grid() {
     }
 }
 
+static void check_permutation_cases(std::mt19937_64 &rng) {
+    int64_t bad = -1;
+    CHECK(check_permutation(nullptr, 0, &bad) == PERM_OK);
+    for (int trial = 0; trial < 20; ++trial) {
+        const int64_t n = 1 + (int64_t)(rng() % 5000);
+        std::vector<int32_t> perm(n);
+        for (int64_t i = 0; i < n; ++i)
+            perm[i] = (int32_t)i;
+        std::shuffle(perm.begin(), perm.end(), rng);
+        CHECK(check_permutation(perm.data(), n, &bad) == PERM_OK);
+        if (n < 2)
+            continue;
+        const int64_t a = (int64_t)(rng() % n), b = (a + 1 + (int64_t)(rng() % (n - 1))) % n;
+        const uint64_t h0 = order_fingerprint(perm.data(), n);
+        std::swap(perm[a], perm[b]);
+        CHECK(check_permutation(perm.data(), n, &bad) == PERM_OK);
+        CHECK(order_fingerprint(perm.data(), n) != h0);     // the order, not the set
+        std::swap(perm[a], perm[b]);
+        CHECK(order_fingerprint(perm.data(), n) == h0);
+        std::vector<int32_t> rep = perm;                   // a row twice, one missing
+        rep[std::max(a, b)] = rep[std::min(a, b)];
+        CHECK(check_permutation(rep.data(), n, &bad) == PERM_REPEAT && bad == std::max(a, b));
+        std::vector<int32_t> out = perm;
+        out[a] = (int32_t)n;
+        CHECK(check_permutation(out.data(), n, &bad) == PERM_RANGE && bad == a);
+        out[a] = -1;
+        CHECK(check_permutation(out.data(), n, &bad) == PERM_RANGE && bad == a);
+    }
+    // FNV-1a's offset basis is the hash of no bytes
+    CHECK(order_fingerprint(nullptr, 0) == 0xcbf29ce484222325ull);
+    // one entry hashes its four little-endian bytes
+    const int32_t one = 0x04030201;
+    uint64_t h = 0xcbf29ce484222325ull;
+    for (int b = 1; b <= 4; ++b) {
+        h ^= (uint64_t)b;
+        h *= 0x100000001b3ull;
+    }
+    CHECK(order_fingerprint(&one, 1) == h);
+}
+
 int main() {
     check_row_ptr_cases();
     std::mt19937_64 rng(7);
@@ -113,6 +154,7 @@ int main() {
     }
     check_heavy_plan({0, 64, 65, 2048, 2049, 3072, 3073, 0});
     check_fused_grid();
+    check_permutation_cases(rng);
     if (failures) {
         fprintf(stderr, "%d checks failed\n", failures);
         return 1;

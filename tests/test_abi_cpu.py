@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(N):
 
 def test_struct_layouts(N):
     o = N.default_options()
-    assert o.struct_size == ctypes.sizeof(N.Options) == 104
+    assert o.struct_size == ctypes.sizeof(N.Options) == 112
     assert ctypes.sizeof(N.CSR) == 48 and ctypes.sizeof(N.Info) == 72
     assert o.eta == 2.0 and o.max_iter == 100 and o.check_every == 16
     assert o.precision == N.FC_PREC_FP32 and o.diag == N.FC_DIAG_UNIT and o.accelerate == 1
