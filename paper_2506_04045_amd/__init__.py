@@ -160,7 +160,12 @@ def history_records(hist: dict, accelerate: bool = True) -> list:
 
 
 class Solver:
-    """One solve of problem (P): fc_create / fc_step / fc_solve / fc_get_u."""
+    """One solve of problem (P): fc_create / fc_step / fc_solve / fc_get_u.
+
+    reorder: "none" (the caller's numbering), "degree" (the library
+    renumbers the articles by descending degree) or an integer array of the
+    n row indices (a given order: internal row i is the caller's row
+    reorder[i]).  Every form returns iterates in the caller's numbering."""
 
     def __init__(self, row_ptr, col_idx, val, c: int, U0=None, *, precision: str = "fp32",
                  diag: str = "unit", accelerate: bool = True, step: float = 0.0,
