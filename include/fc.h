@@ -150,7 +150,8 @@ typedef struct {
  * FC_REORDER_DEGREE bit for bit.  Relabelling needs n < 2^31.  Checkpoints
  * record the mode, and for FC_REORDER_GIVEN a 64-bit fingerprint (FNV-1a) of
  * perm.  fc_set_state rejects a state taken under another numbering.  The
- * serving engine does not accept FC_REORDER_GIVEN (FC_ERR_UNSUPPORTED). */
+ * serving engine checks perm in fc_server_submit and keeps its own copy, so
+ * the caller's array may be released when submit returns. */
 typedef enum { FC_REORDER_NONE = 0, FC_REORDER_DEGREE = 1, FC_REORDER_GIVEN = 2 } fc_reorder;
 
 /* Deferred loss evaluation (defer_loss = 1, constant or scheduled steps only:

@@ -396,7 +396,7 @@ class Server:
 
     def submit(self, req_id: int, row_ptr, col_idx, val, c: int, U0=None, **options) -> None:
         csr = _CsrView(row_ptr, col_idx, val)
-        opt = _options(c, **options)
+        opt = _options(c, n=csr.n, **options)
         u0_ptr, u0_dt = None, N.FC_F32
         if U0 is not None:
             U0 = _dev(U0, "U0", (torch.float64, torch.float32))

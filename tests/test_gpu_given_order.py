@@ -4,7 +4,8 @@ order gives the natural order's iterates up to the order of the
 cross-article sums.  The descending-degree order handed over by the caller
 is the library's own relabelling, so it must reproduce FC_REORDER_DEGREE bit
 for bit.  Invalid orders are rejected on the host before any device work,
-and a checkpoint resumes only under the order it was taken with."""
+a checkpoint resumes only under the order it was taken with, and a served
+request under a given order runs exactly as it does alone."""
 
 import ctypes
 
@@ -120,11 +121,36 @@ def test_checkpoint_resumes_only_under_its_order(fc):
                 d.set_state(state)
 
 
-def test_server_rejects_a_given_order(fc):
+def _poll_for(sv, req_id, timeout_s=60.0):
+    import time
+    t_end = time.time() + timeout_s
+    while time.time() < t_end:
+        for r in sv.poll(timeout_us=20_000):
+            if r.req_id == req_id:
+                return r
+    pytest.fail(f"request {req_id} did not finish")
+
+
+@pytest.mark.parametrize("solo_max", [4, 0], ids=["solo_lane", "batched"])
+def test_served_request_under_a_given_order_is_its_solo_run(fc, solo_max):
     from paper_2506_04045_amd import _native as N
-    wl = W.er_planted(2000, 8, 10.0, 0.05, 3).to("cuda")
-    perm = np.arange(wl.n, dtype=np.int32)[::-1].copy()
-    with fc.Server() as sv:
+    wl = W.er_planted(4000, 16, 15.0, 0.05, 42).to("cuda")
+    perm = np.random.default_rng(8).permutation(wl.n).astype(np.int32)
+    opts = dict(backtrack=True, max_iter=60, tol_pgrad=1e-4)
+    with fc.Solver(wl.row_ptr, wl.col_idx, wl.val, 16, wl.U0, reorder=perm, **opts) as solo:
+        solo.solve()
+        U_solo, f_solo = solo.get_u().cpu().numpy(), solo.info().f
+    with fc.Server(solo_max=solo_max) as sv:
+        bad = perm.copy()
+        bad[3] = bad[0]
         with pytest.raises(N.FcError) as e:
-            sv.submit(1, wl.row_ptr, wl.col_idx, wl.val, 8, wl.U0, reorder=perm)
-        assert e.value.status == N.FC_ERR_UNSUPPORTED
+            sv.submit(1, wl.row_ptr, wl.col_idx, wl.val, 16, wl.U0, reorder=bad, **opts)
+        assert e.value.status == N.FC_ERR_INVALID_ARG
+        # the binding's int32 copy of the order is released when submit
+        # returns; the request runs from the server's own copy
+        sv.submit(2, wl.row_ptr, wl.col_idx, wl.val, 16, wl.U0, reorder=perm, **opts)
+        r = _poll_for(sv, 2)
+        assert r.status == 0 and r.f == f_solo
+        assert np.array_equal(sv.get_u(2).cpu().numpy(), U_solo)
+        sv.release(2)
+        assert sv.stats()["bytes_in_use"] == 0
