@@ -108,6 +108,47 @@ def test_argument_errors_before_device_work(N):
     lib.fc_destroy(None)
 
 
+def test_given_order_errors_before_device_work(N):
+    """FC_REORDER_GIVEN: a missing, repeating or out-of-range order is
+    rejected by fc_create's host-side checks, naming the first bad entry."""
+    lib = N.load()
+    h = ctypes.c_void_p()
+    csr = N.CSR(10, 0, 1, None, None, N.FC_F32)   # fake pointer, never dereferenced
+    opt = N.default_options()
+    opt.c = 4
+    opt.reorder = N.FC_REORDER_GIVEN
+    assert lib.fc_create(ctypes.byref(csr), ctypes.byref(opt), None, N.FC_F32, None,
+                         ctypes.byref(h)) == N.FC_ERR_INVALID_ARG
+    assert b"perm" in lib.fc_last_error() and not h.value
+    for perm, msg in (([0, 1, 2, 3, 4, 5, 6, 7, 8, 8], b"entry 9 repeats"),
+                      ([0, 1, 2, 3, 10, 5, 6, 7, 8, 9], b"entry 4 is outside"),
+                      ([0, 1, -1, 3, 4, 5, 6, 7, 8, 9], b"entry 2 is outside")):
+        arr = (ctypes.c_int32 * 10)(*perm)
+        opt.perm = ctypes.cast(arr, ctypes.POINTER(ctypes.c_int32))
+        assert lib.fc_create(ctypes.byref(csr), ctypes.byref(opt), None, N.FC_F32, None,
+                             ctypes.byref(h)) == N.FC_ERR_INVALID_ARG
+        assert msg in lib.fc_last_error() and not h.value
+    opt.reorder = 3
+    assert lib.fc_create(ctypes.byref(csr), ctypes.byref(opt), None, N.FC_F32, None,
+                         ctypes.byref(h)) == N.FC_ERR_INVALID_ARG
+    assert b"reorder" in lib.fc_last_error()
+
+
+def test_binding_marshals_a_given_order(N):
+    import numpy as np
+    import torch
+    import paper_2506_04045_amd as fc
+    for src in ([3, 0, 2, 1], np.array([3, 0, 2, 1], dtype=np.int64), torch.tensor([3, 0, 2, 1])):
+        opt = fc._options(2, reorder=src, n=4)
+        assert opt.reorder == N.FC_REORDER_GIVEN
+        assert [opt.perm[i] for i in range(4)] == [3, 0, 2, 1]
+    for bad in ([0, 1, 2], [[0, 1], [2, 3]], [0, 1, 2, -1], [0, 1, 2, 2 ** 31]):
+        with pytest.raises(ValueError):
+            fc._options(2, reorder=bad, n=4)
+    assert fc._options(2, reorder="degree").reorder == N.FC_REORDER_DEGREE
+    assert not fc._options(2, reorder="none").perm
+
+
 def test_product_code_does_not_use_the_oracle():
     pkg = os.path.join(ROOT, "paper_2506_04045_amd")
     for dirpath, _, files in os.walk(pkg):
