@@ -123,3 +123,17 @@ def test_bench_refuses_more_than_one_gpu():
     out = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
                          capture_output=True, text=True, timeout=120, cwd=root)
     assert out.returncode == 2 and "one GPU" in out.stderr
+
+
+def test_solver_order_for_each_leg():
+    """The library's orders pass by name; a built order reaches the power-law
+    legs as its array and the other workloads as degree order."""
+    import argparse
+    perm = np.arange(5, dtype=np.int32)[::-1].copy()
+    for name in ("none", "degree"):
+        a = argparse.Namespace(reorder=name)
+        assert bench.solver_order(a) == name and bench.solver_order(a, power_law=False) == name
+    for name in ("cm", "community"):
+        a = argparse.Namespace(reorder=name, given_order=perm)
+        assert bench.solver_order(a) is perm
+        assert bench.solver_order(a, power_law=False) == "degree"
